@@ -1,0 +1,251 @@
+/*
+ * bpx.h - C ABI of the array BP-XOR coded matrix multiplication library
+ * (libbpx.so, HIP for gfx950).
+ *
+ * Method: Arslan, "Array BP-XOR Codes for Hierarchically Distributed Matrix
+ * Multiplication" (arXiv 1904.11563).  The paper computes A^T B over n compute
+ * nodes (Sec. II); a node (column of the code) holds b coded symbols, each the
+ * XOR of a subset of the k*b information symbols (Sec. III-A, definition of
+ * the [n,k,t,b] array BP-XOR code), and the sink recovers the product with the
+ * belief-propagation (peeling) decoder of Sec. I-A from the columns that
+ * arrive first.
+ *
+ * This library computes C = A.B with A (M x K) and B (K x N), all FP32
+ * row-major.  The k*b information symbols are the k*b row-blocks of A
+ * (block s = rows [s*Mb, (s+1)*Mb), Mb = ceil(M/(k*b)), rows past M are zero);
+ * a coded symbol g is the real sum C_g = sum_{s in N(g)} A_s (XOR read as a
+ * real sum, as Table I writes it); each virtual worker multiplies its coded
+ * blocks by B; the peel recovers every A_s.B.
+ *
+ * Conventions for every function:
+ *  - Return value is a bpx_status; on failure bpx_last_error() returns a
+ *    message (thread-local, valid until the next call on the same thread).
+ *  - Handles (bpx_code, bpx_plan) are created and freed by the library and
+ *    are immutable after creation; distinct handles may be used from
+ *    distinct threads.  Arrays returned through "borrowed" pointers live as
+ *    long as the handle.
+ *  - Host functions (code and plan construction, queries) never touch the GPU.
+ *  - Device functions take caller-owned device pointers, enqueue on the given
+ *    HIP stream and return without synchronising.  They allocate nothing
+ *    except the plan's small device tables, which are uploaded on the first
+ *    device call with that plan (or by bpx_plan_upload); call
+ *    bpx_plan_upload before capturing a device call in a HIP graph.
+ *  - Matrices are row-major with leading dimensions in elements.  A, B, C,
+ *    workspaces must be 16-byte aligned and lda, ldb, ldc multiples of 4.
+ *    K must be a multiple of 4.  M, N are arbitrary (>= 1).
+ */
+#ifndef BPX_H
+#define BPX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BPX_OK = 0,
+  BPX_E_INVALID = -1,      /* bad argument                                   */
+  BPX_E_UNDECODABLE = -2,  /* the available columns do not peel               */
+  BPX_E_NOMEM = -3,        /* host or device allocation failed                */
+  BPX_E_HIP = -4,          /* a HIP runtime call failed                       */
+  BPX_E_UNSUPPORTED = -5   /* valid request outside what this build handles   */
+} bpx_status;
+
+typedef enum {
+  BPX_CODE_ARRAY_SEARCH = 0, /* deterministic search for an [n,k,.,b] code    */
+  BPX_CODE_TABLE1 = 1,       /* Table I, the [5,2,.,2] code, sigma = 2         */
+  BPX_CODE_TABLE3 = 2,       /* Table III, the [5,3,2,3] code, sigma = 2       */
+  BPX_CODE_MOJETTE = 3,      /* Mojette code, Construction A or B (Sec. III-C) */
+  BPX_CODE_IDENTITY = 4      /* uncoded layout: n = k columns of b data blocks */
+} bpx_code_kind;
+
+typedef enum {
+  BPX_PREC_F32 = 0,    /* FP32 operands, FP32 MFMA                            */
+  BPX_PREC_BF16 = 1,   /* operands rounded to BF16 (RNE), one MFMA pass       */
+  BPX_PREC_BF16X3 = 2, /* split BF16: hi.hi + hi.lo + lo.hi, FP32 accumulate  */
+  BPX_PREC_FP8 = 3,    /* e4m3 with one FP32 scale per 128x128 block          */
+  BPX_PREC_FP8X2 = 4   /* coded operand split into two e4m3 terms, B one term */
+} bpx_prec;
+
+typedef enum {
+  BPX_MODE_ERASURE = 0,   /* first n - n_lost arrival columns exist; shortest
+                             peelable prefix of them is computed             */
+  BPX_MODE_STRAGGLER = 1, /* all columns arrive; shortest peelable prefix    */
+  BPX_MODE_FULL = 2,      /* every column computed, schedule from all        */
+  BPX_MODE_MIN = 3        /* as STRAGGLER but only the releasers computed    */
+} bpx_mode;
+
+typedef struct {
+  int32_t kind;        /* bpx_code_kind                                       */
+  int32_t n, k, b;     /* columns, data columns, symbols per data column      */
+  int32_t sigma_max;   /* ARRAY_SEARCH: maximum symbol degree (1..k*b)        */
+  int32_t restarts;    /* ARRAY_SEARCH: restarts of the hill-climb            */
+  int32_t iters;       /* ARRAY_SEARCH: iterations per restart                */
+  int32_t mojette_qe;  /* MOJETTE: 0 = Construction A (q = 1),
+                          >= 1 = Construction B (q = 2^qe, odd p)            */
+  uint64_t seed;       /* ARRAY_SEARCH: SplitMix64 seed                       */
+} bpx_code_params;
+
+typedef struct bpx_code bpx_code;
+typedef struct bpx_plan bpx_plan;
+typedef struct ihipStream_t* bpx_stream; /* a hipStream_t; NULL = null stream */
+
+/* ---------------------------------------------------------------- codes -- */
+
+/* Build a code (host, integer only).  Symbols are numbered column by column
+ * (g = symbols in earlier columns + row); data ids of a symbol are sorted.
+ * ARRAY_SEARCH: a hill-climb over random codes driven by one SplitMix64(seed)
+ *   stream, minimising (failing k-column subsets, all-columns-fail flag,
+ *   unrecovered ids summed over failing subsets, peeling rounds summed over
+ *   peelable subsets, total degree); the paper gives no general construction
+ *   for array BP-XOR codes (Sec. III-A/B) so the code is searched.  Needs
+ *   k*b <= 64.  Cost grows with restarts * iters * C(n, k).
+ * TABLE1 / TABLE3: the worked codes of Table I / Table III; v_i -> id i-1.
+ * MOJETTE: n projections over the k x b grid, ascending p; bin of cell
+ *   (z, l) given by Eq. (moj1); data id of (z, l) is l*b + z; empty bins keep
+ *   their index.  Construction A: p = -floor((n-1)/2)..ceil((n-1)/2), q = 1.
+ *   Construction B: odd p = ceil_odd(1-n)..ceil_odd(n-1), q = 2^qe.
+ * IDENTITY: n = k; symbol (j, i) = block j*b + i.
+ * *out receives a new handle (free with bpx_code_free).
+ * Errors: BPX_E_INVALID for out-of-range parameters. */
+bpx_status bpx_code_build(const bpx_code_params* params, bpx_code** out);
+
+/* Build a code from explicit CSR arrays (copied).  col_ptr has n+1 entries
+ * (symbol ranges per column), sym_ptr n_sym+1 entries (id ranges per
+ * symbol), sym_data the ids (each < k*b, strictly ascending per symbol).
+ * Errors: BPX_E_INVALID on malformed arrays. */
+bpx_status bpx_code_from_csr(int32_t n, int32_t k, int32_t b, const int32_t* col_ptr,
+                             const int32_t* sym_ptr, const uint16_t* sym_data,
+                             bpx_code** out);
+
+/* Sizes of a code: columns, k, b, total symbols (empty bins included), total
+ * degree (sum of |N(g)|), maximum degree.  Any pointer may be NULL. */
+bpx_status bpx_code_info(const bpx_code* code, int32_t* n, int32_t* k, int32_t* b,
+                         int32_t* n_sym, int32_t* nnz, int32_t* max_degree);
+
+/* Borrowed views of the code's CSR arrays (see bpx_code_from_csr). */
+bpx_status bpx_code_csr(const bpx_code* code, const int32_t** col_ptr,
+                        const int32_t** sym_ptr, const uint16_t** sym_data);
+
+void bpx_code_free(bpx_code* code);
+
+/* ---------------------------------------------------------------- plans -- */
+
+/* Plan one coded product (host, integer only; no GPU call).
+ * arrival: permutation of the n column ids, earliest first.
+ * n_lost: ERASURE mode only, the number of trailing arrival columns that
+ *   never arrive.
+ * Prefix: the smallest m such that the non-empty symbols of the first m
+ *   arrival columns peel (peeling success only grows with m, so the scan is
+ *   exact); the time-to-decode of Eq. (1) for this arrival order.
+ * Schedule: round-based peeling (Sec. I-A).  In round r every symbol with
+ *   exactly one unknown id is a candidate; each id released in round r takes
+ *   the candidate with the smallest (degree, g) as releaser g_s, gets depth
+ *   r, and sub_s = N(g_s) \ {s}; all ids of a round become known together.
+ * Computed symbols: every non-empty symbol of the first m columns (FULL: of
+ *   all columns; MIN: only the releasers), ascending g.
+ * M, K, N: the product's shape; prec: bpx_prec of the device path.
+ * Returns BPX_OK, or BPX_E_UNDECODABLE when the available columns do not
+ * peel; in that case *out is still a valid, queryable plan (its schedule
+ * covers what was recovered) and every device call with it returns
+ * BPX_E_UNDECODABLE without writing anything. */
+bpx_status bpx_plan_create(const bpx_code* code, const int32_t* arrival, int32_t n_arrival,
+                           int32_t n_lost, int32_t mode, int64_t M, int64_t K, int64_t N,
+                           int32_t prec, bpx_plan** out);
+
+/* Scalar facts of a plan; any pointer may be NULL.  Mb = ceil(M/(k*b)).
+ * depth_max = the largest release round. */
+bpx_status bpx_plan_info(const bpx_plan* plan, int32_t* decodable, int32_t* prefix_m,
+                         int32_t* n_computed, int32_t* depth_max, int32_t* n_unrecovered,
+                         int64_t* Mb);
+
+/* Borrowed views of the schedule.
+ * computed[n_computed]: computed symbol ids, ascending.
+ * dest[n_computed]: where the coded product of computed[i] is written by
+ *   bpx_coded_gemm: dest >= 0 is a slot of the Y workspace (slot d occupies
+ *   floats [d*Mb*N, (d+1)*Mb*N), row-major Mb x N); dest < 0 means the
+ *   product is written straight into C rows of data block (-1 - dest)
+ *   (a degree-1 releaser).
+ * releaser[kb], depth[kb]: g_s and the release round of each data id (-1 and
+ *   0 if not recovered).
+ * sub_ptr[kb+1], sub_data: sub_s = N(g_s) \ {s}, ascending.
+ * unrecovered[n_unrecovered]: ids not recovered.  Any pointer may be NULL. */
+bpx_status bpx_plan_schedule(const bpx_plan* plan, const int32_t** computed,
+                             const int32_t** dest, const int32_t** releaser,
+                             const int32_t** depth, const int32_t** sub_ptr,
+                             const uint16_t** sub_data, const int32_t** unrecovered);
+
+/* Device workspace the plan needs for bpx_coded_gemm / bpx_coded_matmul
+ * (Y slots and, for FP8, quantised operands and scales), and the size of the
+ * buffer bpx_encode writes (n_computed coded blocks of Mb x K floats). */
+bpx_status bpx_plan_workspace_bytes(const bpx_plan* plan, size_t* ws_bytes,
+                                    size_t* encode_bytes);
+
+/* Upload the plan's device tables now (hipMalloc + synchronous copy on the
+ * current device).  Device calls do this on first use otherwise. */
+bpx_status bpx_plan_upload(bpx_plan* plan);
+
+void bpx_plan_free(bpx_plan* plan);
+
+/* --------------------------------------------------------------- device -- */
+
+/* Encode only: write C_g = sum_{s in N(g)} A_s (FP32, ascending s) for every
+ * computed symbol, block i of coded_out (ld = K) holding computed[i].  The
+ * master-side encode of Sec. II; exists for tests and encode bandwidth.
+ * coded_out must hold encode_bytes (bpx_plan_workspace_bytes). */
+bpx_status bpx_encode(bpx_plan* plan, const float* A, int64_t lda, float* coded_out,
+                      bpx_stream stream);
+
+/* Coded products: Y_g = C_g . B for every computed symbol, the encode fused
+ * into the A-operand load (the coded block is never stored).  Products go to
+ * the Y slots of ws or, for degree-1 releasers, straight into C (see dest in
+ * bpx_plan_schedule).  Precision is the plan's.  ws must hold ws_bytes. */
+bpx_status bpx_coded_gemm(bpx_plan* plan, const float* A, int64_t lda, const float* B,
+                          int64_t ldb, float* C, int64_t ldc, void* ws, size_t ws_bytes,
+                          bpx_stream stream);
+
+/* Peel: in (depth, s) order, X_s = Y_{g_s} - sum_{u in sub_s} X_u, written to
+ * C rows of block s (rows past M are not written).  Accumulation is FP32
+ * compensated (Kahan) where depth_s <= 4 and FP64 where depth_s > 4.
+ * Reads the Y slots of ws and the C blocks of degree-1 releasers. */
+bpx_status bpx_peel_decode(bpx_plan* plan, const void* ws, size_t ws_bytes, float* C,
+                           int64_t ldc, bpx_stream stream);
+
+/* bpx_coded_gemm followed by bpx_peel_decode on the same stream. */
+bpx_status bpx_coded_matmul(bpx_plan* plan, const float* A, int64_t lda, const float* B,
+                            int64_t ldb, float* C, int64_t ldc, void* ws, size_t ws_bytes,
+                            bpx_stream stream);
+
+/* Many independent coded products in one launch sequence.  plans[i] gives
+ * product i's code, arrival pattern, shape and precision (all plans must
+ * share one precision); A[i], B[i], C[i] are its operands with leading
+ * dimensions equal to K, N, N.  ws must hold the sum over i of each plan's
+ * ws_bytes rounded up to 256 bytes, plus bpx_grouped_extra_bytes(count).
+ * Any undecodable plan makes the call return BPX_E_UNDECODABLE before any
+ * launch. */
+bpx_status bpx_coded_matmul_grouped(bpx_plan* const* plans, const float* const* A,
+                                    const float* const* B, float* const* C, int32_t count,
+                                    void* ws, size_t ws_bytes, bpx_stream stream);
+
+/* Extra workspace bytes the grouped call needs for its descriptors. */
+size_t bpx_grouped_extra_bytes(int32_t count);
+
+/* Tile-shape selection: the grouped and single-product GEMM pick one of the
+ * compiled tile shapes per product.  bpx_tile_count() returns the number of
+ * shapes; bpx_set_tile_table installs an autotuned table mapping shape
+ * buckets (log2 of M/128, N/128, K/128 clamped to [0, 7], and the precision)
+ * to a tile-shape index; entries < 0 fall back to the default choice.  The
+ * table has 8*8*8*5 entries indexed ((prec*8 + bm)*8 + bn)*8 + bk. */
+int32_t bpx_tile_count(void);
+bpx_status bpx_set_tile_table(const int32_t* table, int32_t n_entries);
+/* Force one tile shape for every call (for the autotuner); -1 = table. */
+bpx_status bpx_force_tile(int32_t tile);
+
+const char* bpx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BPX_H */

@@ -1,0 +1,29 @@
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")
+    config.addinivalue_line("markers", "slow: long CPU test")
+
+
+def load_golden_table(name):
+    """Parse a golden table fixture into columns of sorted 0-based id tuples."""
+    path = os.path.join(ROOT, "tests", "golden", name)
+    cols = []
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            _, rhs = line.split(":", 1)
+            col = []
+            for cell in rhs.split("|"):
+                ids = sorted(int(x) - 1 for x in cell.strip().split("+"))
+                col.append(tuple(ids))
+            cols.append(col)
+    return cols

@@ -1,0 +1,258 @@
+"""Pins of the oracle's code objects against what the paper fixes.
+
+Every test here runs on the CPU and touches only ``oracle/``.
+"""
+from itertools import combinations
+from math import ceil
+
+import pytest
+
+from conftest import load_golden_table
+from oracle import codes
+from oracle.peeling import peel
+from oracle.splitmix import SplitMix64
+
+
+def _peels(symbols, kb):
+    rel, _ = peel(symbols, kb)
+    return len(rel) == kb
+
+
+def _col_syms(code, cols):
+    return [(g, d) for g, j, d in code.symbols() if j in set(cols)]
+
+
+# ------------------------------------------------------------- SplitMix64 --
+
+def test_splitmix64_published_vector():
+    # Published first outputs of SplitMix64 seeded with 0.
+    r = SplitMix64(0)
+    assert [r.next() for _ in range(3)] == [
+        0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+# ------------------------------------------------------- Tables I and III --
+
+def test_table1_matches_paper_fixture():
+    assert codes.table1().columns == load_golden_table("table1.txt")
+
+
+def test_table3_matches_paper_fixture():
+    assert codes.table3().columns == load_golden_table("table3.txt")
+
+
+def test_table1_any_two_nodes_decode():
+    # Sec. III-A after Table I: any two of the five nodes suffice.
+    c = codes.table1()
+    for sub in combinations(range(5), 2):
+        assert _peels(_col_syms(c, sub), c.kb), sub
+    # and no single node does (2 symbols for 4 unknowns)
+    for j in range(5):
+        assert not _peels(_col_syms(c, [j]), c.kb)
+
+
+def test_table1_recovery_threshold_is_seven():
+    # Sec. III-A after Table I: any 7 processor outputs suffice; 7 is the
+    # threshold, so some set of 6 does not.
+    c = codes.table1()
+    syms = [(g, d) for g, _, d in c.symbols()]
+    assert all(_peels(list(s), c.kb) for s in combinations(syms, 7))
+    assert not all(_peels(list(s), c.kb) for s in combinations(syms, 6))
+
+
+def test_table3_any_three_nodes_decode():
+    # [5,3,2,3] block-MDS: any n - t = 3 columns reconstruct (Sec. III-A).
+    c = codes.table3()
+    for sub in combinations(range(5), 3):
+        assert _peels(_col_syms(c, sub), c.kb), sub
+    for sub in combinations(range(5), 2):
+        assert not _peels(_col_syms(c, sub), c.kb)
+
+
+def test_tables_max_degree_sigma_two():
+    assert codes.table1().max_degree() == 2
+    assert codes.table3().max_degree() == 2
+
+
+def test_information_symbols_appear_enough():
+    # Proof of the Thm. on n (Sec. III-B): in a block-MDS code tolerating n-k
+    # column erasures every information symbol appears in >= n-k+1 columns.
+    for c in (codes.table1(), codes.table3()):
+        for s in range(c.kb):
+            cols = {j for _, j, d in c.symbols() if s in d}
+            assert len(cols) >= c.n - c.k + 1
+
+
+# ----------------------------------------------------------------- Mojette --
+
+SMALL = [(k, b) for k in range(1, 7) for b in range(1, 7)]
+
+
+@pytest.mark.parametrize("k,b", SMALL)
+def test_mojette_bin_count_closed_form(k, b):
+    # b_i = |p|(k-1) + |q|(b-1) + 1 (Sec. III-C) against the index map of
+    # Eq. (moj1): every index in range is reachable from the ends and the
+    # number of indices equals the closed form.
+    for p in range(-6, 7):
+        for q in range(0, 5):
+            if q == 0 and p == 0:
+                continue
+            from math import gcd
+            if gcd(p, q) != 1:
+                continue
+            col = codes.mojette_column(p, q, k, b)
+            assert len(col) == codes.mojette_bin_count(p, q, k, b)
+            # every cell lands in exactly one bin
+            ids = sorted(x for sym in col for x in sym)
+            assert ids == list(range(k * b))
+            # the first and last bins are never empty
+            assert len(col[0]) > 0 and len(col[-1]) > 0
+
+
+@pytest.mark.parametrize("k,b", SMALL)
+def test_mojette_max_degree_theorem(k, b):
+    # sigma_i = min(ceil(b/|p|), ceil(k/|q|)) (degree theorem, Sec. III-C)
+    from math import gcd
+    for p in range(-6, 7):
+        for q in range(1, 5):
+            if gcd(p, q) != 1:
+                continue
+            col = codes.mojette_column(p, q, k, b)
+            assert max(len(s) for s in col) == codes.mojette_max_degree(p, q, k, b)
+
+
+def test_construction_a_lists():
+    # Construction A: p from -floor((n-1)/2) to ceil((n-1)/2), n values.
+    assert codes.construction_a_p(5) == [-2, -1, 0, 1, 2]
+    assert codes.construction_a_p(4) == [-1, 0, 1, 2]
+    assert codes.construction_a_p(24) == list(range(-11, 13))
+    for n in range(1, 40):
+        assert len(codes.construction_a_p(n)) == n
+
+
+def test_construction_b_lists():
+    # Construction B: odd p from ceil_odd(-n+1) to ceil_odd(n-1): n values.
+    assert codes.construction_b_p(5) == [-3, -1, 1, 3, 5]
+    assert codes.construction_b_p(4) == [-3, -1, 1, 3]
+    for n in range(1, 40):
+        ps = codes.construction_b_p(n)
+        assert len(ps) == n and all(p % 2 for p in ps)
+
+
+def test_lemma_a1():
+    # Lemma A.1: sum of |p| over t projections of Construction A is
+    # (t^2-1)/4 for odd t and t^2/4 for even t.
+    for t in range(1, 60):
+        direct = sum(abs(p) for p in codes.construction_a_p(t))
+        assert codes.lemma_a1(t) == direct
+        assert direct == ((t * t - 1) // 4 if t % 2 else t * t // 4)
+
+
+def test_lemma_b1():
+    # Lemma B.1: sum of |p| over t projections of Construction B.
+    for t in range(1, 60):
+        direct = sum(abs(p) for p in codes.construction_b_p(t))
+        assert codes.lemma_b1(t) == direct
+
+
+@pytest.mark.parametrize("qe", [0, 1, 2])
+def test_katz_implies_peeling(qe):
+    # Katz criterion (Sec. III-C): sum|p| >= b or sum|q| >= k => BP succeeds.
+    for k in range(2, 6):
+        for b in range(2, 6):
+            n = 5
+            c = codes.mojette(k, b, n, qe)
+            for t in range(1, n + 1):
+                for sub in combinations(range(n), t):
+                    projs = [c.projections[i] for i in sub]
+                    if codes.katz(projs, k, b):
+                        assert _peels(_col_syms(c, sub), c.kb), (k, b, qe, sub)
+
+
+def test_construction_a_any_k_projections_decode():
+    # Construction A: any k projections have sum|q| = k, so they decode.
+    for k in range(2, 6):
+        for b in range(2, 8):
+            n = k + 3
+            c = codes.mojette(k, b, n, 0)
+            for sub in combinations(range(n), k):
+                assert _peels(_col_syms(c, sub), c.kb)
+
+
+def test_construction_a_overhead_exact():
+    # Appendix A: the worst-case overhead of Construction A is
+    # (k-1)/(2kb) (phi(n)+phi(n-1)-phi(n-k)-phi(n-k-1)), checked against the
+    # direct maximum over every k-column choice of the built code.
+    for n in range(2, 12):
+        for k in range(1, n):
+            for b in (1, 2, 3, 5, 8):
+                c = codes.mojette(k, b, n, 0)
+                direct = codes.overhead_direct(c, k)
+                assert abs(direct - codes.overhead_closed_a(n, k, b)) < 1e-12, (n, k, b)
+                # bracket of Appendix A
+                lo = (k - 1) / (4 * k * b) * (2 * k * n - k * k - 1)
+                hi = (k - 1) / (4 * k * b) * (2 * k * n - k * k + 1)
+                assert lo - 1e-12 <= direct <= hi + 1e-12
+
+
+def test_overhead_k16_n24_b8():
+    # The Mojette code of the FP8 workload: k=16, n=24, b=8, Construction A.
+    assert codes.overhead_closed_a(24, 16, 8) == 15.0
+    assert codes.overhead_approx_a(24, 16, 8) == 15 * 32 / 32
+
+
+def test_mojette_large_p_columns_are_copies():
+    # With |p| >= b every bin holds at most one cell (degree theorem with
+    # ceil(b/|p|) = 1): such a projection alone recovers the grid.
+    c = codes.mojette(16, 8, 24, 0)
+    for j, (p, q) in enumerate(c.projections):
+        if abs(p) >= 8:
+            assert max(len(s) for s in c.columns[j]) == 1
+            assert _peels(_col_syms(c, [j]), c.kb)
+
+
+# ------------------------------------------------------------ array search --
+
+def _brute_objective(code):
+    """Objective of the search recounted with the set-based peeler."""
+    n, k, kb = code.n, code.k, code.kb
+    U = L = D = 0
+    for sub in combinations(range(n), k):
+        rel, dep = peel(_col_syms(code, sub), kb)
+        if len(rel) == kb:
+            D += max(dep.values())
+        else:
+            U += 1
+            L += kb - len(rel)
+    F = 0 if _peels(_col_syms(code, range(n)), kb) else 1
+    return U, F, L, D
+
+
+def test_search_objective_recount():
+    rng = SplitMix64(7)
+    for trial in range(6):
+        n, k, b, sig = [(6, 4, 2, 3), (5, 3, 2, 2), (7, 4, 2, 4)][trial % 3]
+        c = codes.array_search(n, k, b, sig, seed=trial, restarts=1, iters=rng.below(5))
+        masks = [[sum(1 << x for x in s) for s in col] for col in c.columns]
+        assert codes.search_objective(masks, k, (1 << (k * b)) - 1) == _brute_objective(c)
+
+
+def test_search_deterministic_and_valid():
+    a = codes.array_search(6, 4, 2, 3, seed=11, restarts=2, iters=40)
+    b = codes.array_search(6, 4, 2, 3, seed=11, restarts=2, iters=40)
+    assert a.columns == b.columns
+    for col in a.columns:
+        assert len(col) == 2
+        for s in col:
+            assert 1 <= len(s) <= 3 and list(s) == sorted(set(s))
+            assert all(0 <= x < 8 for x in s)
+
+
+def test_search_642_not_column_mds():
+    # A peelable k-column system is invertible over GF(2), so a column-MDS
+    # BP-XOR code is an MDS code over an alphabet of size 2^b; the Bush bound
+    # (k >= q => n <= k+1) rules out n = 6, k = 4, q = 4.  The search result
+    # must therefore leave at least one failing 4-column subset.
+    c = codes.array_search(6, 4, 2, 3, seed=0, restarts=2, iters=300)
+    U, F, _, _ = _brute_objective(c)
+    assert U >= 1 and F == 0
