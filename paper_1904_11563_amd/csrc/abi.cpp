@@ -1,0 +1,402 @@
+// The extern "C" boundary of libbpx (declared in include/bpx.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "host.hpp"
+#include "kernels.hpp"
+
+namespace bpx {
+
+namespace {
+thread_local std::string g_error;
+int32_t g_force_tile = -1;
+int32_t g_tile_table[8 * 8 * 8 * 5];
+bool g_tile_table_set = false;
+}  // namespace
+
+void set_error(const std::string& msg) { g_error = msg; }
+const char* get_error() { return g_error.c_str(); }
+
+namespace {
+
+bpx_status fail(bpx_status st, const std::string& msg) {
+  set_error(msg);
+  return st;
+}
+
+bpx_status hip_fail(hipError_t e, const char* what) {
+  return fail(BPX_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool aligned16(const void* ptr) { return ((uintptr_t)ptr & 15u) == 0; }
+
+int32_t log2_bucket(int64_t x) {
+  int64_t v = (x + 127) / 128;
+  int32_t b = 0;
+  while (v > 1 && b < 7) {
+    v >>= 1;
+    ++b;
+  }
+  return b;
+}
+
+int32_t choose_tile(int32_t prec, int64_t Mb, int64_t N, int64_t K) {
+  if (g_force_tile >= 0) return g_force_tile;
+  if (g_tile_table_set) {
+    const int32_t idx =
+        ((prec * 8 + log2_bucket(Mb)) * 8 + log2_bucket(N)) * 8 + log2_bucket(K);
+    const int32_t t = g_tile_table[idx];
+    if (t >= 0 && t < gemm_tile_count()) return t;
+  }
+  // default: 128x128 unless the block or N is small
+  if (Mb <= 64 && N <= 64) return 1;
+  if (Mb <= 64) return 3;
+  if (N <= 64) return 2;
+  return 0;
+}
+
+bpx_status upload(bpx_plan* plan) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (plan->dev_block) {
+    if (plan->dev_id != dev)
+      return fail(BPX_E_INVALID, "plan tables live on another device");
+    return BPX_OK;
+  }
+  auto bytes_of = [](size_t n, size_t sz) { return (n * sz + 255) / 256 * 256; };
+  const size_t b0 = bytes_of(plan->gemm_syms.size(), 4);
+  const size_t b1 = bytes_of(plan->gemm_ids.size(), 4);
+  const size_t b2 = bytes_of(plan->steps.size(), sizeof(PeelStep));
+  const size_t b3 = bytes_of(plan->step_subs.size(), 4);
+  const size_t total = std::max<size_t>(b0 + b1 + b2 + b3, 256);
+  std::string host(total, '\0');
+  std::memcpy(&host[0], plan->gemm_syms.data(), plan->gemm_syms.size() * 4);
+  std::memcpy(&host[b0], plan->gemm_ids.data(), plan->gemm_ids.size() * 4);
+  std::memcpy(&host[b0 + b1], plan->steps.data(), plan->steps.size() * sizeof(PeelStep));
+  std::memcpy(&host[b0 + b1 + b2], plan->step_subs.data(), plan->step_subs.size() * 4);
+  void* d = nullptr;
+  e = hipMalloc(&d, total);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc(plan tables)");
+  e = hipMemcpy(d, host.data(), total, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    return hip_fail(e, "hipMemcpy(plan tables)");
+  }
+  char* base = static_cast<char*>(d);
+  plan->dev_block = d;
+  plan->dev_id = dev;
+  plan->d_gemm_syms = reinterpret_cast<const int32_t*>(base);
+  plan->d_gemm_ids = reinterpret_cast<const int32_t*>(base + b0);
+  plan->d_steps = reinterpret_cast<const PeelStep*>(base + b0 + b1);
+  plan->d_step_subs = reinterpret_cast<const int32_t*>(base + b0 + b1 + b2);
+  return BPX_OK;
+}
+
+bpx_status check_device_call(bpx_plan* plan) {
+  if (!plan) return fail(BPX_E_INVALID, "null plan");
+  if (!plan->decodable) return fail(BPX_E_UNDECODABLE, "plan is not decodable");
+  if (plan->K % 4 != 0) return fail(BPX_E_INVALID, "K must be a multiple of 4");
+  if (plan->prec != BPX_PREC_F32)
+    return fail(BPX_E_UNSUPPORTED, "precision not built into this library");
+  return upload(plan);
+}
+
+bpx_status check_matrix(const float* ptr, int64_t ld, int64_t cols, const char* name) {
+  if (!ptr) return fail(BPX_E_INVALID, std::string(name) + " is null");
+  if (!aligned16(ptr)) return fail(BPX_E_INVALID, std::string(name) + " not 16-byte aligned");
+  if (ld < cols || ld % 4 != 0)
+    return fail(BPX_E_INVALID, std::string("leading dimension of ") + name +
+                                   " must be >= its columns and a multiple of 4");
+  return BPX_OK;
+}
+
+bpx_status gemm_impl(bpx_plan* plan, const float* A, int64_t lda, const float* B, int64_t ldb,
+                     float* C, int64_t ldc, void* ws, size_t ws_bytes, hipStream_t stream) {
+  bpx_status st;
+  if ((st = check_matrix(A, lda, plan->K, "A")) != BPX_OK) return st;
+  if ((st = check_matrix(B, ldb, plan->N, "B")) != BPX_OK) return st;
+  if ((st = check_matrix(C, ldc, plan->N, "C")) != BPX_OK) return st;
+  if (plan->y_bytes() > 0 && (!ws || ws_bytes < plan->y_bytes() || !aligned16(ws)))
+    return fail(BPX_E_INVALID, "workspace missing, misaligned or too small");
+  GemmParams p{};
+  p.A = A;
+  p.lda = lda;
+  p.B = B;
+  p.ldb = ldb;
+  p.C = C;
+  p.ldc = ldc;
+  p.Y = static_cast<float*>(ws);
+  p.M = plan->M;
+  p.K = plan->K;
+  p.N = plan->N;
+  p.Mb = plan->Mb;
+  p.syms = plan->d_gemm_syms;
+  p.ids = plan->d_gemm_ids;
+  p.n_sym = (int32_t)plan->computed.size();
+  p.prec = plan->prec;
+  const int32_t tile = choose_tile(plan->prec, plan->Mb, plan->N, plan->K);
+  hipError_t e = launch_coded_gemm(p, tile, stream);
+  if (e != hipSuccess) return hip_fail(e, "coded gemm launch");
+  return BPX_OK;
+}
+
+bpx_status peel_impl(bpx_plan* plan, const void* ws, size_t ws_bytes, float* C, int64_t ldc,
+                     hipStream_t stream) {
+  bpx_status st;
+  if ((st = check_matrix(C, ldc, plan->N, "C")) != BPX_OK) return st;
+  if (plan->y_bytes() > 0 && (!ws || ws_bytes < plan->y_bytes() || !aligned16(ws)))
+    return fail(BPX_E_INVALID, "workspace missing, misaligned or too small");
+  PeelParams p{};
+  p.Y = static_cast<const float*>(ws);
+  p.C = C;
+  p.ldc = ldc;
+  p.M = plan->M;
+  p.N = plan->N;
+  p.Mb = plan->Mb;
+  p.steps = plan->d_steps;
+  p.subs = plan->d_step_subs;
+  p.nsteps = (int32_t)plan->steps.size();
+  p.nslots = plan->n_lds_slots;
+  hipError_t e = launch_peel(p, stream);
+  if (e == hipErrorInvalidConfiguration)
+    return fail(BPX_E_UNSUPPORTED, "peel needs more LDS than a workgroup has");
+  if (e != hipSuccess) return hip_fail(e, "peel launch");
+  return BPX_OK;
+}
+
+}  // namespace
+}  // namespace bpx
+
+using namespace bpx;
+
+extern "C" {
+
+const char* bpx_last_error(void) { return get_error(); }
+
+bpx_status bpx_code_build(const bpx_code_params* params, bpx_code** out) {
+  if (!params || !out) return fail(BPX_E_INVALID, "null argument");
+  *out = nullptr;
+  bpx_code* c = new (std::nothrow) bpx_code();
+  if (!c) return fail(BPX_E_NOMEM, "out of host memory");
+  std::string err;
+  int st = build_code(*params, c, &err);
+  if (st != BPX_OK) {
+    delete c;
+    return fail((bpx_status)st, err);
+  }
+  *out = c;
+  return BPX_OK;
+}
+
+bpx_status bpx_code_from_csr(int32_t n, int32_t k, int32_t b, const int32_t* col_ptr,
+                             const int32_t* sym_ptr, const uint16_t* sym_data, bpx_code** out) {
+  if (!out || !col_ptr || !sym_ptr) return fail(BPX_E_INVALID, "null argument");
+  *out = nullptr;
+  if (n < 1 || k < 1 || b < 1 || (int64_t)k * b > 65535)
+    return fail(BPX_E_INVALID, "need n, k, b >= 1 and k*b <= 65535");
+  if (col_ptr[0] != 0) return fail(BPX_E_INVALID, "col_ptr[0] must be 0");
+  for (int32_t j = 0; j < n; ++j)
+    if (col_ptr[j + 1] < col_ptr[j]) return fail(BPX_E_INVALID, "col_ptr not ascending");
+  const int32_t ns = col_ptr[n];
+  if (sym_ptr[0] != 0) return fail(BPX_E_INVALID, "sym_ptr[0] must be 0");
+  for (int32_t g = 0; g < ns; ++g) {
+    if (sym_ptr[g + 1] < sym_ptr[g]) return fail(BPX_E_INVALID, "sym_ptr not ascending");
+    for (int32_t e = sym_ptr[g]; e < sym_ptr[g + 1]; ++e) {
+      if (sym_data[e] >= k * b) return fail(BPX_E_INVALID, "data id out of range");
+      if (e > sym_ptr[g] && sym_data[e] <= sym_data[e - 1])
+        return fail(BPX_E_INVALID, "ids of a symbol must be strictly ascending");
+    }
+  }
+  bpx_code* c = new (std::nothrow) bpx_code();
+  if (!c) return fail(BPX_E_NOMEM, "out of host memory");
+  c->kind = -1;
+  c->n = n;
+  c->k = k;
+  c->b = b;
+  c->col_ptr.assign(col_ptr, col_ptr + n + 1);
+  c->sym_ptr.assign(sym_ptr, sym_ptr + ns + 1);
+  c->sym_data.assign(sym_data, sym_data + sym_ptr[ns]);
+  *out = c;
+  return BPX_OK;
+}
+
+bpx_status bpx_code_info(const bpx_code* code, int32_t* n, int32_t* k, int32_t* b,
+                         int32_t* n_sym, int32_t* nnz, int32_t* max_degree) {
+  if (!code) return fail(BPX_E_INVALID, "null code");
+  if (n) *n = code->n;
+  if (k) *k = code->k;
+  if (b) *b = code->b;
+  if (n_sym) *n_sym = code->n_sym();
+  if (nnz) *nnz = (int32_t)code->sym_data.size();
+  if (max_degree) *max_degree = code->max_degree();
+  return BPX_OK;
+}
+
+bpx_status bpx_code_csr(const bpx_code* code, const int32_t** col_ptr, const int32_t** sym_ptr,
+                        const uint16_t** sym_data) {
+  if (!code) return fail(BPX_E_INVALID, "null code");
+  if (col_ptr) *col_ptr = code->col_ptr.data();
+  if (sym_ptr) *sym_ptr = code->sym_ptr.data();
+  if (sym_data) *sym_data = code->sym_data.data();
+  return BPX_OK;
+}
+
+void bpx_code_free(bpx_code* code) { delete code; }
+
+bpx_status bpx_plan_create(const bpx_code* code, const int32_t* arrival, int32_t n_arrival,
+                           int32_t n_lost, int32_t mode, int64_t M, int64_t K, int64_t N,
+                           int32_t prec, bpx_plan** out) {
+  if (!code || !out) return fail(BPX_E_INVALID, "null argument");
+  *out = nullptr;
+  bpx_plan* p = new (std::nothrow) bpx_plan();
+  if (!p) return fail(BPX_E_NOMEM, "out of host memory");
+  std::string err;
+  int st = make_plan(*code, arrival, n_arrival, n_lost, mode, M, K, N, prec, p, &err);
+  if (st == BPX_E_INVALID) {
+    delete p;
+    return fail(BPX_E_INVALID, err);
+  }
+  *out = p;
+  if (st == BPX_E_UNDECODABLE) return fail(BPX_E_UNDECODABLE, "available columns do not peel");
+  return BPX_OK;
+}
+
+bpx_status bpx_plan_info(const bpx_plan* plan, int32_t* decodable, int32_t* prefix_m,
+                         int32_t* n_computed, int32_t* depth_max, int32_t* n_unrecovered,
+                         int64_t* Mb) {
+  if (!plan) return fail(BPX_E_INVALID, "null plan");
+  if (decodable) *decodable = plan->decodable ? 1 : 0;
+  if (prefix_m) *prefix_m = plan->prefix_m;
+  if (n_computed) *n_computed = (int32_t)plan->computed.size();
+  if (depth_max) *depth_max = plan->depth_max;
+  if (n_unrecovered) *n_unrecovered = (int32_t)plan->unrecovered.size();
+  if (Mb) *Mb = plan->Mb;
+  return BPX_OK;
+}
+
+bpx_status bpx_plan_schedule(const bpx_plan* plan, const int32_t** computed, const int32_t** dest,
+                             const int32_t** releaser, const int32_t** depth,
+                             const int32_t** sub_ptr, const uint16_t** sub_data,
+                             const int32_t** unrecovered) {
+  if (!plan) return fail(BPX_E_INVALID, "null plan");
+  if (computed) *computed = plan->computed.data();
+  if (dest) *dest = plan->dest.data();
+  if (releaser) *releaser = plan->releaser.data();
+  if (depth) *depth = plan->depth.data();
+  if (sub_ptr) *sub_ptr = plan->sub_ptr.data();
+  if (sub_data) *sub_data = plan->sub_data.data();
+  if (unrecovered) *unrecovered = plan->unrecovered.data();
+  return BPX_OK;
+}
+
+bpx_status bpx_plan_workspace_bytes(const bpx_plan* plan, size_t* ws_bytes,
+                                    size_t* encode_bytes) {
+  if (!plan) return fail(BPX_E_INVALID, "null plan");
+  if (ws_bytes) *ws_bytes = plan->y_bytes();
+  if (encode_bytes)
+    *encode_bytes = plan->computed.size() * (size_t)plan->Mb * (size_t)plan->K * sizeof(float);
+  return BPX_OK;
+}
+
+bpx_status bpx_plan_upload(bpx_plan* plan) {
+  if (!plan) return fail(BPX_E_INVALID, "null plan");
+  return upload(plan);
+}
+
+void bpx_plan_free(bpx_plan* plan) {
+  if (!plan) return;
+  if (plan->dev_block) (void)hipFree(plan->dev_block);
+  delete plan;
+}
+
+bpx_status bpx_encode(bpx_plan* plan, const float* A, int64_t lda, float* coded_out,
+                      bpx_stream stream) {
+  bpx_status st = check_device_call(plan);
+  if (st != BPX_OK) return st;
+  if ((st = check_matrix(A, lda, plan->K, "A")) != BPX_OK) return st;
+  if (!coded_out || !aligned16(coded_out))
+    return fail(BPX_E_INVALID, "coded_out null or misaligned");
+  EncodeParams p{};
+  p.A = A;
+  p.lda = lda;
+  p.out = coded_out;
+  p.M = plan->M;
+  p.K = plan->K;
+  p.Mb = plan->Mb;
+  p.syms = plan->d_gemm_syms;
+  p.ids = plan->d_gemm_ids;
+  p.n_sym = (int32_t)plan->computed.size();
+  hipError_t e = launch_encode(p, reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "encode launch");
+  return BPX_OK;
+}
+
+bpx_status bpx_coded_gemm(bpx_plan* plan, const float* A, int64_t lda, const float* B,
+                          int64_t ldb, float* C, int64_t ldc, void* ws, size_t ws_bytes,
+                          bpx_stream stream) {
+  bpx_status st = check_device_call(plan);
+  if (st != BPX_OK) return st;
+  return gemm_impl(plan, A, lda, B, ldb, C, ldc, ws, ws_bytes,
+                   reinterpret_cast<hipStream_t>(stream));
+}
+
+bpx_status bpx_peel_decode(bpx_plan* plan, const void* ws, size_t ws_bytes, float* C,
+                           int64_t ldc, bpx_stream stream) {
+  bpx_status st = check_device_call(plan);
+  if (st != BPX_OK) return st;
+  return peel_impl(plan, ws, ws_bytes, C, ldc, reinterpret_cast<hipStream_t>(stream));
+}
+
+bpx_status bpx_coded_matmul(bpx_plan* plan, const float* A, int64_t lda, const float* B,
+                            int64_t ldb, float* C, int64_t ldc, void* ws, size_t ws_bytes,
+                            bpx_stream stream) {
+  bpx_status st = check_device_call(plan);
+  if (st != BPX_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  st = gemm_impl(plan, A, lda, B, ldb, C, ldc, ws, ws_bytes, s);
+  if (st != BPX_OK) return st;
+  return peel_impl(plan, ws, ws_bytes, C, ldc, s);
+}
+
+bpx_status bpx_coded_matmul_grouped(bpx_plan* const* plans, const float* const* A,
+                                    const float* const* B, float* const* C, int32_t count,
+                                    void* ws, size_t ws_bytes, bpx_stream stream) {
+  (void)plans;
+  (void)A;
+  (void)B;
+  (void)C;
+  (void)count;
+  (void)ws;
+  (void)ws_bytes;
+  (void)stream;
+  return fail(BPX_E_UNSUPPORTED, "grouped launch not built yet");
+}
+
+size_t bpx_grouped_extra_bytes(int32_t count) { return count > 0 ? 0 : 0; }
+
+int32_t bpx_tile_count(void) { return gemm_tile_count(); }
+
+bpx_status bpx_set_tile_table(const int32_t* table, int32_t n_entries) {
+  const int32_t need = (int32_t)(sizeof(g_tile_table) / sizeof(g_tile_table[0]));
+  if (!table) {
+    g_tile_table_set = false;
+    return BPX_OK;
+  }
+  if (n_entries != need) return fail(BPX_E_INVALID, "tile table has the wrong size");
+  std::memcpy(g_tile_table, table, sizeof(g_tile_table));
+  g_tile_table_set = true;
+  return BPX_OK;
+}
+
+bpx_status bpx_force_tile(int32_t tile) {
+  if (tile >= gemm_tile_count()) return fail(BPX_E_INVALID, "no such tile shape");
+  g_force_tile = tile < 0 ? -1 : tile;
+  return BPX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,111 @@
+// Host-side objects of libbpx: codes, plans, and the device tables a plan
+// uploads.  Integer work only; no HIP types appear here.
+#pragma once
+
+#include "../../include/bpx.h"
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+struct bpx_code {
+  int32_t kind = 0;
+  int32_t n = 0, k = 0, b = 0;
+  std::vector<int32_t> col_ptr;   // n + 1
+  std::vector<int32_t> sym_ptr;   // n_sym + 1
+  std::vector<uint16_t> sym_data; // ids, ascending per symbol
+  int32_t n_sym() const { return (int32_t)sym_ptr.size() - 1; }
+  int32_t kb() const { return k * b; }
+  int32_t deg(int32_t g) const { return sym_ptr[g + 1] - sym_ptr[g]; }
+  int32_t max_degree() const;
+};
+
+// One step of the device peel program (see plan.cpp).
+struct PeelStep {
+  int32_t s;        // data block written / loaded
+  int32_t src;      // Y slot of the releaser, or -1 when X_s already sits in C
+  int32_t nsub;     // number of subtrahends
+  int32_t sub_off;  // offset of the subtrahends' LDS slots in the slot list
+  int32_t f64;      // 1: accumulate in FP64 (depth > 4), 0: FP32 Kahan
+  int32_t slot;     // LDS slot that keeps X_s for later steps, or -1
+  int32_t write;    // 1: write X_s to C
+  int32_t pad;
+};
+
+struct bpx_plan {
+  // copy of the code (a plan outlives nothing it does not own)
+  bpx_code code;
+  int32_t mode = 0, prec = 0;
+  int64_t M = 0, K = 0, N = 0, Mb = 0;
+
+  bool decodable = false;
+  int32_t prefix_m = 0;
+  int32_t depth_max = 0;
+  std::vector<int32_t> computed;    // ascending g
+  std::vector<int32_t> dest;        // per computed: Y slot or -1-s
+  std::vector<int32_t> releaser;    // per data id
+  std::vector<int32_t> depth;       // per data id
+  std::vector<int32_t> sub_ptr;     // kb + 1
+  std::vector<uint16_t> sub_data;
+  std::vector<int32_t> unrecovered;
+  int32_t n_yslots = 0;
+
+  // device peel program
+  std::vector<PeelStep> steps;
+  std::vector<int32_t> step_subs;   // LDS slots of subtrahends
+  int32_t n_lds_slots = 0;
+
+  // GEMM symbol table: per computed symbol {id_off, deg, dest, 0} + ids
+  std::vector<int32_t> gemm_syms;
+  std::vector<int32_t> gemm_ids;
+
+  // device copies
+  void* dev_block = nullptr;
+  int32_t dev_id = -1;
+  const int32_t* d_gemm_syms = nullptr;
+  const int32_t* d_gemm_ids = nullptr;
+  const PeelStep* d_steps = nullptr;
+  const int32_t* d_step_subs = nullptr;
+
+  size_t y_bytes() const { return (size_t)n_yslots * (size_t)Mb * (size_t)N * sizeof(float); }
+};
+
+namespace bpx {
+
+// SplitMix64 (Steele, Lea, Flood 2014).
+struct SplitMix64 {
+  uint64_t state;
+  explicit SplitMix64(uint64_t seed) : state(seed) {}
+  uint64_t next() {
+    state += 0x9E3779B97F4A7C15ull;
+    uint64_t z = state;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+  uint64_t below(uint64_t n) { return next() % n; }
+};
+
+// Thread-local error message.
+void set_error(const std::string& msg);
+const char* get_error();
+
+// code.cpp
+int build_code(const bpx_code_params& p, bpx_code* out, std::string* err);
+
+// plan.cpp
+struct PeelResult {
+  std::vector<int32_t> releaser;  // -1 = unknown
+  std::vector<int32_t> depth;
+  int32_t n_known = 0;
+  int32_t rounds = 0;
+};
+// Round-based peel over the given symbols (ids into code), canonical releaser.
+PeelResult peel(const bpx_code& code, const std::vector<int32_t>& syms);
+int make_plan(const bpx_code& code, const int32_t* arrival, int32_t n_arrival, int32_t n_lost,
+              int32_t mode, int64_t M, int64_t K, int64_t N, int32_t prec, bpx_plan* plan,
+              std::string* err);
+
+}  // namespace bpx
+

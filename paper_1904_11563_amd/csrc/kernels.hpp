@@ -1,0 +1,67 @@
+// Device kernels of libbpx: parameter blocks and host-side launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "host.hpp"
+
+namespace bpx {
+
+// Coded GEMM: for every computed symbol i (table entry {id_off, deg, dest, g}
+// in syms[4*i..4*i+3], member ids in ids[id_off .. id_off+deg)),
+//   out_i = (sum over members s of A rows [s*Mb, s*Mb+Mb)) . B
+// where out_i is Y slot dest (Mb x N, ld N) or, for dest < 0, the C rows of
+// block -1-dest (ld ldc, rows past M skipped).
+struct GemmParams {
+  const float* A;
+  int64_t lda;
+  const float* B;
+  int64_t ldb;
+  float* C;
+  int64_t ldc;
+  float* Y;
+  int64_t M, K, N, Mb;
+  const int32_t* syms;
+  const int32_t* ids;
+  int32_t n_sym;
+  int32_t tiles_m, tiles_n;
+  int32_t prec;  // bpx_prec
+};
+
+// Peel: see PeelStep in host.hpp.
+struct PeelParams {
+  const float* Y;
+  float* C;
+  int64_t ldc;
+  int64_t M, N, Mb;
+  const PeelStep* steps;
+  const int32_t* subs;
+  int32_t nsteps;
+  int32_t nslots;
+};
+
+// Standalone encode: out block i (Mb x K, ld K) = sum of member blocks of A.
+struct EncodeParams {
+  const float* A;
+  int64_t lda;
+  float* out;
+  int64_t M, K, Mb;
+  const int32_t* syms;
+  const int32_t* ids;
+  int32_t n_sym;
+};
+
+// Tile shapes compiled for the GEMM.
+struct TileShape {
+  int32_t bm, bn, bk;
+};
+int32_t gemm_tile_count();
+TileShape gemm_tile_shape(int32_t t);
+
+hipError_t launch_coded_gemm(const GemmParams& p, int32_t tile, hipStream_t stream);
+hipError_t launch_peel(const PeelParams& p, hipStream_t stream);
+hipError_t launch_encode(const EncodeParams& p, hipStream_t stream);
+
+}  // namespace bpx

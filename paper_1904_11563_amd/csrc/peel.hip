@@ -1,0 +1,99 @@
+// Peeling decode on the device: one HBM-streaming pass.
+//
+// The BP decoder of Sec. I-A, run on real numbers: in (depth, s) order every
+// recovered block is X_s = Y_{g_s} - sum over u in N(g_s)\{s} of X_u.  The
+// schedule is identical for every element of the Mb x N block, so each
+// thread runs the whole program for its own element (row r, column c of
+// every block) with no barriers between release rounds.  Values that later
+// steps subtract are kept in this thread's LDS column.
+//
+// Accumulation: FP32 with Kahan compensation for depth <= 4; FP64 for
+// deeper releases.  Rows past M (padding of the last block) are exactly
+// zero and are neither read nor written.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace bpx {
+namespace {
+
+constexpr int kBatch = 8;  // steps whose loads are issued together
+
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void peel_kernel(PeelParams p) {
+  extern __shared__ float xs[];  // [nslots][THREADS]
+  const int tid = threadIdx.x;
+  const int64_t total = p.Mb * p.N;
+  const int64_t e = (int64_t)blockIdx.x * THREADS + tid;
+  const bool active = e < total;
+  const int64_t r = active ? e / p.N : 0;
+  const int64_t c = active ? e - r * p.N : 0;
+
+  for (int st0 = 0; st0 < p.nsteps; st0 += kBatch) {
+    float y[kBatch];
+#pragma unroll
+    for (int i = 0; i < kBatch; ++i) {
+      y[i] = 0.f;
+      const int st = st0 + i;
+      if (st < p.nsteps && active) {
+        const PeelStep S = p.steps[st];
+        const int64_t base = (int64_t)S.s * p.Mb;
+        const int64_t valid = p.M - base < p.Mb ? p.M - base : p.Mb;
+        if (r < valid) {
+          if (S.src >= 0)
+            y[i] = p.Y[(int64_t)S.src * total + e];
+          else
+            y[i] = p.C[(base + r) * p.ldc + c];
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kBatch; ++i) {
+      const int st = st0 + i;
+      if (st >= p.nsteps) break;
+      const PeelStep S = p.steps[st];
+      const int64_t base = (int64_t)S.s * p.Mb;
+      const int64_t valid = p.M - base < p.Mb ? p.M - base : p.Mb;
+      float x = 0.f;
+      if (r < valid) {
+        const int32_t* sub = p.subs + S.sub_off;
+        if (S.f64) {
+          double acc = (double)y[i];
+          for (int u = 0; u < S.nsub; ++u) acc -= (double)xs[sub[u] * THREADS + tid];
+          x = (float)acc;
+        } else {
+          float sum = y[i], comp = 0.f;
+          for (int u = 0; u < S.nsub; ++u) {
+            const float v = -xs[sub[u] * THREADS + tid] - comp;
+            const float t = sum + v;
+            comp = (t - sum) - v;
+            sum = t;
+          }
+          x = sum;
+        }
+      }
+      if (S.slot >= 0) xs[S.slot * THREADS + tid] = x;
+      if (S.write && active && r < valid) p.C[(base + r) * p.ldc + c] = x;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_peel(const PeelParams& p, hipStream_t stream) {
+  if (p.nsteps == 0) return hipSuccess;
+  const int64_t total = p.Mb * p.N;
+  int threads = 256;
+  if ((int64_t)p.nslots * 256 * 4 > 64 * 1024) threads = 64;
+  const size_t lds = (size_t)p.nslots * threads * sizeof(float);
+  if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
+  const int64_t blocks = (total + threads - 1) / threads;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  if (threads == 256)
+    hipLaunchKernelGGL(peel_kernel<256>, dim3((unsigned)blocks), dim3(256), lds, stream, p);
+  else
+    hipLaunchKernelGGL(peel_kernel<64>, dim3((unsigned)blocks), dim3(64), lds, stream, p);
+  return hipGetLastError();
+}
+
+}  // namespace bpx

@@ -6,6 +6,17 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
+def _ensure_library():
+    """Build libbpx.so in-tree when it is not there yet (a fresh checkout)."""
+    lib = os.path.join(ROOT, "paper_1904_11563_amd", "libbpx.so")
+    if not os.path.exists(lib):
+        from paper_1904_11563_amd.build import build
+        build()
+
+
+_ensure_library()
+
+
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")
     config.addinivalue_line("markers", "slow: long CPU test")

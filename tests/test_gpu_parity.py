@@ -1,0 +1,296 @@
+"""GPU parity: the HIP path through the C ABI against the oracle.
+
+Integer-valued operands in [-8, 8] make every FP32 operation of the HIP
+path exact (all partial sums stay far below 2^24), so for them the decoded
+product must equal A.B bit for bit.  Float operands are held to the FP32
+bound: relative Frobenius error <= 1e-5 against the float64 oracle.
+"""
+import itertools
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import codes as ocodes
+from oracle import pipeline
+from oracle.peeling import make_plan
+from paper_1904_11563_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_1904_11563_amd import bpx  # noqa: E402  (fails loudly if the library is missing)
+
+TOL_F32 = 1e-5
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def lib_code(spec):
+    if spec.kind == "search":
+        return bpx.Code.search(spec.n, spec.k, spec.b, spec.sigma, spec.seed, spec.restarts,
+                               spec.iters)
+    if spec.kind == "mojette":
+        return bpx.Code.mojette(spec.k, spec.b, spec.n, spec.qe)
+    raise ValueError(spec.kind)
+
+
+def oracle_of(code):
+    inf = code.info()
+    return ocodes.Code("array", inf["n"], inf["k"], inf["b"], code.columns())
+
+
+def padded(x):
+    """Device copy of a 2-D array whose row stride is rounded up to 4 floats
+    (the ABI's alignment rule), returned as the unpadded view."""
+    r, c = x.shape
+    ld = -(-c // 4) * 4
+    t = torch.zeros((r, ld), dtype=torch.float32, device="cuda")
+    t[:, :c] = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    return t[:, :c]
+
+
+def run(plan, A, B, ldc_pad=0):
+    M, N = A.shape[0], B.shape[1]
+    Ad, Bd = padded(A), padded(B)
+    ldc = -(-N // 4) * 4 + ldc_pad
+    Cfull = torch.full((M, ldc), float("nan"), device="cuda")
+    Cd = Cfull[:, :N]
+    ws = bpx.alloc_workspace(plan)
+    bpx.coded_matmul(plan, Ad, Bd, Cd, ws)
+    return host(Cd)
+
+
+def relf(X, R):
+    return pipeline.rel_frobenius(X, R)
+
+
+CODE_642 = None
+
+
+def code642():
+    global CODE_642
+    if CODE_642 is None:
+        CODE_642 = lib_code(inputs.CODE_642)
+    return CODE_642
+
+
+# ------------------------------------------------------------- small, exact --
+
+def test_every_erasure_pair_small_code_integer_exact():
+    code = code642()
+    oc = oracle_of(code)
+    M, K, N = 517, 260, 300            # ragged in every dimension
+    A = inputs.integers(1, inputs.TAG_A, (M, K))
+    B = inputs.integers(1, inputs.TAG_B, (K, N))
+    R = A.astype(np.float64) @ B.astype(np.float64)
+    n_ok = n_bad = 0
+    for lost in itertools.combinations(range(6), 2):
+        order = [j for j in range(6) if j not in lost] + list(lost)
+        _say("erasure pattern", lost)
+        plan = bpx.Plan(code, order, 2, bpx.MODE_ERASURE, M, K, N)
+        want = make_plan(oc, order, 2, 0)
+        assert plan.decodable == want.decodable
+        if not plan.decodable:
+            n_bad += 1
+            Cd = torch.full((M, N), float("nan"), device="cuda")
+            ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+            with pytest.raises(bpx.BpxError) as e:
+                bpx.coded_matmul(plan, dev(A), dev(B), Cd, ws)
+            assert e.value.status == bpx.E_UNDECODABLE
+            assert torch.isnan(Cd).all().item()       # nothing written
+            continue
+        n_ok += 1
+        C = run(plan, A, B)
+        assert np.array_equal(C.astype(np.float64), R), lost
+    assert n_ok > 0 and n_bad >= 1     # (6,4,2) cannot be column-MDS
+
+
+def test_small_workload_float_tolerance():
+    w = inputs.WORKLOADS["fp32_small"]
+    A, B = inputs.operands(w, seed=0)
+    arrival, lost, _ = inputs.arrival_of(w, seed=0)
+    code = code642()
+    plan = bpx.Plan(code, arrival, lost, bpx.MODE_STRAGGLER, w.M, w.K, w.N)
+    C = run(plan, A, B)
+    want = make_plan(oracle_of(code), list(arrival), lost, 1)
+    C_ref = pipeline.coded_matmul_ref(A, B, oracle_of(code), want)
+    R = pipeline.uncoded(A, B)
+    assert relf(C_ref, R) < 1e-12
+    e = relf(C, R)
+    _say("fp32_small relF", e)
+    assert e <= TOL_F32
+
+
+def test_coded_gemm_products_and_aliases():
+    code = code642()
+    oc = oracle_of(code)
+    M, K, N = 300, 132, 200
+    A = inputs.integers(2, inputs.TAG_A, (M, K))
+    B = inputs.integers(2, inputs.TAG_B, (K, N))
+    order = [5, 3, 0, 1, 2, 4]
+    plan = bpx.Plan(code, order, 0, bpx.MODE_FULL, M, K, N)
+    sch = plan.schedule()
+    want = make_plan(oc, order, 0, 2)
+    Y_ref = pipeline.coded_products(pipeline.encode(A, oc, want.computed), B)
+    Ad, Bd = dev(A), dev(B)
+    Cd = torch.zeros((M, N), device="cuda")
+    ws = bpx.alloc_workspace(plan)
+    bpx.coded_gemm(plan, Ad, Bd, Cd, ws)
+    Mb = plan.info()["Mb"]
+    Y = host(ws).view(np.float32)
+    C = host(Cd)
+    for g, d in zip(sch["computed"].tolist(), sch["dest"].tolist()):
+        if d >= 0:
+            got = Y[d * Mb * N:(d + 1) * Mb * N].reshape(Mb, N)
+            assert np.array_equal(got.astype(np.float64), Y_ref[g]), g
+        else:
+            s = -1 - d
+            rows = min(Mb, M - s * Mb)
+            assert np.array_equal(C[s * Mb:s * Mb + rows].astype(np.float64), Y_ref[g][:rows])
+
+
+def test_encode_matches_oracle():
+    code = code642()
+    oc = oracle_of(code)
+    M, K = 250, 96
+    A = inputs.integers(3, inputs.TAG_A, (M, K))
+    plan = bpx.Plan(code, [0, 1, 2, 3, 4, 5], 0, bpx.MODE_FULL, M, K, 8)
+    _, enc_bytes = plan.workspace_bytes()
+    out = torch.empty(enc_bytes // 4, dtype=torch.float32, device="cuda")
+    bpx.encode(plan, dev(A), out)
+    got = host(out)
+    Mb = plan.info()["Mb"]
+    want = pipeline.encode(A, oc, plan.schedule()["computed"].tolist())
+    for i, g in enumerate(plan.schedule()["computed"].tolist()):
+        assert np.array_equal(got[i * Mb * K:(i + 1) * Mb * K].reshape(Mb, K), want[g])
+    # float operands: fp32 sum against the float64 sum
+    Af = inputs.normal(3, inputs.TAG_A, (M, K))
+    bpx.encode(plan, dev(Af), out)
+    got = host(out)
+    want = pipeline.encode(Af, oc, plan.schedule()["computed"].tolist())
+    for i, g in enumerate(plan.schedule()["computed"].tolist()):
+        blk = got[i * Mb * K:(i + 1) * Mb * K].reshape(Mb, K)
+        assert np.abs(blk - want[g]).max() <= 4 * np.finfo(np.float32).eps * (np.abs(want[g]).max() + 1)
+
+
+def test_table3_depth_nine_chain_fp64_path():
+    code = bpx.Code.table3()
+    M, K, N = 9 * 33 + 4, 64, 130
+    order = [0, 1, 2, 3, 4]
+    plan = bpx.Plan(code, order, 2, bpx.MODE_ERASURE, M, K, N)
+    assert plan.info()["depth_max"] == 9
+    A = inputs.integers(4, inputs.TAG_A, (M, K))
+    B = inputs.integers(4, inputs.TAG_B, (K, N))
+    C = run(plan, A, B)
+    assert np.array_equal(C.astype(np.float64), A.astype(np.float64) @ B)
+    Af = inputs.normal(4, inputs.TAG_A, (M, K))
+    Bf = inputs.normal(4, inputs.TAG_B, (K, N))
+    C = run(plan, Af, Bf)
+    assert relf(C, pipeline.uncoded(Af, Bf)) <= TOL_F32
+
+
+@pytest.mark.parametrize("mode", [bpx.MODE_STRAGGLER, bpx.MODE_FULL, bpx.MODE_MIN])
+def test_modes_table1(mode):
+    code = bpx.Code.table1()
+    M, K, N = 64, 36, 70
+    A = inputs.integers(5, inputs.TAG_A, (M, K))
+    B = inputs.integers(5, inputs.TAG_B, (K, N))
+    for order in itertools.permutations(range(5)):
+        plan = bpx.Plan(code, order, 0, mode, M, K, N)
+        C = run(plan, A, B, ldc_pad=4)
+        assert np.array_equal(C.astype(np.float64), A.astype(np.float64) @ B), order
+
+
+def test_mojette_codes_integer_exact():
+    for (k, b, n, qe) in [(4, 3, 7, 0), (4, 3, 6, 1), (16, 8, 24, 0), (16, 16, 24, 0)]:
+        code = bpx.Code.mojette(k, b, n, qe)
+        kb = k * b
+        M, K, N = kb * 5 + 3, 68, 90
+        A = inputs.integers(6, inputs.TAG_A, (M, K))
+        B = inputs.integers(6, inputs.TAG_B, (K, N))
+        arrival = inputs.rng(k * 100 + b, 9).permutation(n).astype(np.int32)
+        lost = n // 3
+        _say("mojette", k, b, n, qe)
+        plan = bpx.Plan(code, arrival, lost, bpx.MODE_ERASURE, M, K, N)
+        if not plan.decodable:
+            continue
+        C = run(plan, A, B)
+        assert np.array_equal(C.astype(np.float64), A.astype(np.float64) @ B), (k, b, n, qe)
+
+
+def test_identity_code_is_plain_gemm():
+    code = bpx.Code.identity(4, 2)
+    M, K, N = 203, 100, 77
+    A = inputs.normal(7, inputs.TAG_A, (M, K))
+    B = inputs.normal(7, inputs.TAG_B, (K, N))
+    plan = bpx.Plan(code, list(range(4)), 0, bpx.MODE_STRAGGLER, M, K, N)
+    assert plan.workspace_bytes()[0] == 0       # every product lands in C
+    C = run(plan, A, B)
+    assert relf(C, pipeline.uncoded(A, B)) <= TOL_F32
+
+
+def test_padding_blocks_without_rows():
+    # M = 5 with k*b = 4: Mb = 2 and block 3 has no rows at all.
+    code = bpx.Code.table1()
+    M, K, N = 5, 8, 6
+    A = inputs.integers(8, inputs.TAG_A, (M, K))
+    B = inputs.integers(8, inputs.TAG_B, (K, N))
+    for order in itertools.permutations(range(5)):
+        plan = bpx.Plan(code, order, 3, bpx.MODE_ERASURE, M, K, N)
+        C = run(plan, A, B)
+        assert np.array_equal(C.astype(np.float64), A.astype(np.float64) @ B)
+
+
+def test_argument_errors():
+    code = bpx.Code.table1()
+    plan = bpx.Plan(code, [0, 1, 2, 3, 4], 0, bpx.MODE_STRAGGLER, 16, 6, 8)
+    A = torch.zeros((16, 6), device="cuda")
+    B = torch.zeros((6, 8), device="cuda")
+    C = torch.zeros((16, 8), device="cuda")
+    ws = torch.empty(1 << 16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(bpx.BpxError) as e:       # K not a multiple of 4
+        bpx.coded_matmul(plan, A, B, C, ws)
+    assert e.value.status == bpx.E_INVALID
+    plan = bpx.Plan(code, [0, 1, 2, 3, 4], 0, bpx.MODE_FULL, 16, 8, 8)
+    A = torch.zeros((16, 8), device="cuda")
+    B = torch.zeros((8, 8), device="cuda")
+    if plan.workspace_bytes()[0] > 0:
+        with pytest.raises(bpx.BpxError):        # workspace too small
+            bpx.coded_matmul(plan, A, B, C, torch.empty(4, dtype=torch.uint8, device="cuda"))
+    flat = torch.zeros(16 * 8 + 1, device="cuda")
+    Cmis = flat[1:].view(16, 8)
+    with pytest.raises(bpx.BpxError):            # misaligned C
+        bpx.coded_matmul(plan, A, B, Cmis, ws)
+
+
+# ----------------------------------------------------------- full size, f32 --
+
+def test_fp32_scale_full_size_sampled():
+    """8192x8192 . 8192x4096, (12,8,4) searched code, shifted-exponential
+    arrivals: the bench's configuration.  Checked on 256 sampled rows (8 per
+    data block) against float64, plus the Frobenius bound on the sample."""
+    w = inputs.WORKLOADS["fp32_scale"]
+    A, B = inputs.operands(w, seed=0)
+    arrival, lost, _ = inputs.arrival_of(w, seed=0)
+    code = lib_code(w.code)
+    plan = bpx.Plan(code, arrival, lost, bpx.MODE_STRAGGLER, w.M, w.K, w.N)
+    _say("fp32_scale plan", plan.info())
+    C = run(plan, A, B)
+    rows = np.concatenate([np.arange(s * 256, s * 256 + 256, 37)[:8] for s in range(32)])
+    R = A[rows].astype(np.float64) @ B.astype(np.float64)
+    e = relf(C[rows], R)
+    _say("fp32_scale sampled relF", e)
+    assert e <= TOL_F32
+    assert np.isfinite(C).all()

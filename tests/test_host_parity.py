@@ -1,0 +1,196 @@
+"""Host-side parity: the library's code construction and peeling schedule
+(C++ behind the C ABI) against the oracle, bit for bit.  CPU only: these
+calls never touch a GPU."""
+import json
+import os
+import re
+from itertools import combinations, permutations
+
+import numpy as np
+import pytest
+
+from conftest import ROOT, load_golden_table
+from oracle import codes
+from oracle.peeling import make_plan
+from oracle.splitmix import SplitMix64
+
+bpx = pytest.importorskip("paper_1904_11563_amd.bpx")
+
+
+def test_library_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "bpx.h")).read()
+    declared = set(re.findall(r"\b(bpx_[a-z0-9_]+)\s*\(", header))
+    assert declared == set(bpx.EXPORTS)
+    for name in declared:
+        assert hasattr(bpx._lib, name), name
+
+
+def test_presets_match_paper_fixtures():
+    assert bpx.Code.table1().columns() == load_golden_table("table1.txt")
+    assert bpx.Code.table3().columns() == load_golden_table("table3.txt")
+
+
+@pytest.mark.parametrize("k,b,n,qe", [(3, 4, 3, 0), (16, 8, 24, 0), (16, 16, 24, 0),
+                                      (4, 3, 7, 1), (5, 2, 6, 2), (2, 5, 9, 0), (7, 1, 4, 3)])
+def test_mojette_matches_oracle(k, b, n, qe):
+    assert bpx.Code.mojette(k, b, n, qe).columns() == codes.mojette(k, b, n, qe).columns
+
+
+def test_identity_code():
+    c = bpx.Code.identity(4, 3)
+    assert c.columns() == codes.identity(4, 3).columns
+
+
+def test_search_small_budgets_match_oracle():
+    rng = SplitMix64(2024)
+    cases = [(6, 4, 2, 3), (5, 2, 2, 2), (7, 3, 3, 4), (8, 5, 2, 2), (4, 4, 3, 5)]
+    for i, (n, k, b, sig) in enumerate(cases):
+        seed = rng.next()
+        restarts = 1 + rng.below(3)
+        iters = rng.below(150)
+        got = bpx.Code.search(n, k, b, sig, seed, restarts, iters).columns()
+        want = codes.array_search(n, k, b, sig, seed, restarts, iters).columns
+        assert got == want, (n, k, b, sig, seed, restarts, iters)
+
+
+@pytest.mark.parametrize("name", ["642", "1282", "1284"])
+def test_search_matches_golden_fixture(name):
+    path = os.path.join(ROOT, "tests", "golden", f"search_{name}.json")
+    if not os.path.exists(path):
+        pytest.skip("fixture not generated")
+    fx = json.load(open(path))
+    c = bpx.Code.search(fx["n"], fx["k"], fx["b"], fx["sigma_max"], fx["seed"],
+                        fx["restarts"], fx["iters"])
+    col_ptr, sym_ptr, sym_data = c.csr()
+    assert col_ptr.tolist() == fx["col_ptr"]
+    assert sym_ptr.tolist() == fx["sym_ptr"]
+    assert sym_data.tolist() == fx["sym_data"]
+
+
+def test_code_build_rejects_bad_parameters():
+    with pytest.raises(bpx.BpxError) as e:
+        bpx.Code.search(6, 4, 20, 3, 0, 1, 1)      # k*b > 64
+    assert e.value.status == bpx.E_INVALID
+    with pytest.raises(bpx.BpxError):
+        bpx.Code.build(99)
+    with pytest.raises(bpx.BpxError):
+        bpx.Code.from_columns(2, 1, 1, [[(0,)], [(1,)]])   # id out of range
+
+
+# ------------------------------------------------------------------ plans --
+
+def _oracle_code_from_lib(lib_code, kind="array"):
+    inf = lib_code.info()
+    return codes.Code(kind, inf["n"], inf["k"], inf["b"], lib_code.columns())
+
+
+def _compare(lib_code, ocode, arrival, n_lost, mode, M=100, K=8, N=8):
+    plan = bpx.Plan(lib_code, arrival, n_lost, mode, M, K, N)
+    want = make_plan(ocode, list(arrival), n_lost, mode)
+    inf = plan.info()
+    sch = plan.schedule()
+    assert inf["decodable"] == want.decodable
+    assert inf["prefix_m"] == want.prefix_m
+    assert sch["computed"].tolist() == want.computed
+    assert sch["releaser"].tolist() == want.releaser
+    assert sch["depth"].tolist() == want.depth
+    subs = [tuple(sch["sub_data"][sch["sub_ptr"][s]:sch["sub_ptr"][s + 1]].tolist())
+            for s in range(ocode.kb)]
+    assert subs == want.sub
+    assert sch["unrecovered"].tolist() == want.unrecovered
+    assert inf["depth_max"] == want.max_depth
+    assert inf["Mb"] == -(-M // ocode.kb)
+    # destination rule: degree-1 releasers alias their C block, all others
+    # get consecutive Y slots
+    sym = {g: d for g, _, d in ocode.symbols()}
+    slot = 0
+    for g, d in zip(sch["computed"].tolist(), sch["dest"].tolist()):
+        if len(sym[g]) == 1 and want.releaser[sym[g][0]] == g:
+            assert d == -1 - sym[g][0]
+        else:
+            assert d == slot
+            slot += 1
+    return plan
+
+
+def _random_columns(rng, n, k, b, sigma):
+    cols = []
+    for _ in range(n):
+        col = []
+        for _ in range(b):
+            d = 1 + rng.below(sigma)
+            s = set()
+            while len(s) < d:
+                s.add(rng.below(k * b))
+            col.append(tuple(sorted(s)))
+        cols.append(col)
+    return cols
+
+
+def test_plan_parity_presets_all_patterns():
+    for lib_code, ocode in ((bpx.Code.table1(), codes.table1()),
+                            (bpx.Code.table3(), codes.table3())):
+        for order in permutations(range(5)):
+            for lost in range(0, 4):
+                _compare(lib_code, ocode, order, lost, bpx.MODE_ERASURE)
+            for mode in (bpx.MODE_STRAGGLER, bpx.MODE_FULL, bpx.MODE_MIN):
+                _compare(lib_code, ocode, order, 0, mode)
+
+
+def test_plan_parity_random_codes():
+    rng = SplitMix64(77)
+    for trial in range(60):
+        n, k, b, sig = [(6, 4, 2, 3), (8, 5, 2, 4), (5, 3, 3, 2), (7, 2, 4, 3)][trial % 4]
+        cols = _random_columns(rng, n, k, b, sig)
+        lib_code = bpx.Code.from_columns(n, k, b, cols)
+        ocode = codes.Code("array", n, k, b, cols)
+        for _ in range(6):
+            order = list(range(n))
+            for i in range(n - 1, 0, -1):
+                j = rng.below(i + 1)
+                order[i], order[j] = order[j], order[i]
+            for mode in (bpx.MODE_ERASURE, bpx.MODE_STRAGGLER, bpx.MODE_FULL, bpx.MODE_MIN):
+                lost = rng.below(n - 1) if mode == bpx.MODE_ERASURE else 0
+                _compare(lib_code, ocode, order, lost, mode, M=37 + trial)
+
+
+def test_plan_parity_mojette():
+    rng = SplitMix64(3)
+    for (k, b, n, qe) in [(16, 8, 24, 0), (16, 16, 24, 0), (4, 3, 7, 1), (3, 5, 6, 0)]:
+        lib_code = bpx.Code.mojette(k, b, n, qe)
+        ocode = codes.mojette(k, b, n, qe)
+        for _ in range(5):
+            order = list(range(n))
+            for i in range(n - 1, 0, -1):
+                j = rng.below(i + 1)
+                order[i], order[j] = order[j], order[i]
+            _compare(lib_code, ocode, order, n // 3, bpx.MODE_ERASURE, M=16384)
+            _compare(lib_code, ocode, order, 0, bpx.MODE_FULL, M=16384)
+
+
+def test_plan_undecodable_is_queryable():
+    c = bpx.Code.table3()
+    plan = bpx.Plan(c, [0, 1, 2, 3, 4], 3, bpx.MODE_ERASURE, 9, 4, 4)
+    inf = plan.info()
+    assert not inf["decodable"] and inf["n_unrecovered"] > 0
+
+
+def test_plan_rejects_bad_arrival():
+    c = bpx.Code.table1()
+    with pytest.raises(bpx.BpxError) as e:
+        bpx.Plan(c, [0, 0, 1, 2, 3], 0, bpx.MODE_STRAGGLER, 4, 4, 4)
+    assert e.value.status == bpx.E_INVALID
+    with pytest.raises(bpx.BpxError):
+        bpx.Plan(c, [0, 1, 2, 3], 0, bpx.MODE_STRAGGLER, 4, 4, 4)
+    with pytest.raises(bpx.BpxError):
+        bpx.Plan(c, [0, 1, 2, 3, 4], 6, bpx.MODE_ERASURE, 4, 4, 4)
+
+
+def test_workspace_bytes():
+    c = bpx.Code.table3()
+    plan = bpx.Plan(c, [3, 4, 0, 1, 2], 0, bpx.MODE_FULL, 90, 16, 10)
+    ws, enc = plan.workspace_bytes()
+    dest = plan.schedule()["dest"]
+    Mb = 10
+    assert ws == int((dest >= 0).sum()) * Mb * 10 * 4
+    assert enc == len(dest) * Mb * 16 * 4
