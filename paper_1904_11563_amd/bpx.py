@@ -184,9 +184,12 @@ class Code:
         return out
 
     def __del__(self):
-        if getattr(self, "_h", None) and self._h.value:
-            _lib.bpx_code_free(self._h)
-            self._h = _p()
+        try:
+            if getattr(self, "_h", None) and self._h.value:
+                _lib.bpx_code_free(self._h)
+                self._h = _p()
+        except Exception:        # interpreter shutdown
+            pass
 
 
 # ------------------------------------------------------------------ plans --
@@ -251,9 +254,12 @@ class Plan:
         _check(_lib.bpx_plan_upload(self._h))
 
     def __del__(self):
-        if getattr(self, "_h", None) and self._h.value:
-            _lib.bpx_plan_free(self._h)
-            self._h = _p()
+        try:
+            if getattr(self, "_h", None) and self._h.value:
+                _lib.bpx_plan_free(self._h)
+                self._h = _p()
+        except Exception:        # interpreter shutdown
+            pass
 
 
 # ----------------------------------------------------------------- device --

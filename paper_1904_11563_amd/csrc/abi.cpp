@@ -52,10 +52,10 @@ int32_t choose_tile(int32_t prec, int64_t Mb, int64_t N, int64_t K) {
     const int32_t t = g_tile_table[idx];
     if (t >= 0 && t < gemm_tile_count()) return t;
   }
-  // default: 128x128 unless the block or N is small
-  if (Mb <= 64 && N <= 64) return 1;
-  if (Mb <= 64) return 3;
-  if (N <= 64) return 2;
+  // default: 128x128 unless the block is small
+  (void)N;
+  (void)K;
+  if (Mb <= 64) return 1;
   return 0;
 }
 
@@ -139,6 +139,10 @@ bpx_status gemm_impl(bpx_plan* plan, const float* A, int64_t lda, const float* B
   p.ids = plan->d_gemm_ids;
   p.n_sym = (int32_t)plan->computed.size();
   p.prec = plan->prec;
+  // The GEMM kernels index A rows of a block and B rows of a K-slice with
+  // 32-bit offsets.
+  if ((plan->Mb + 256) * lda >= ((int64_t)1 << 31) || 64 * ldb + plan->N >= ((int64_t)1 << 31))
+    return fail(BPX_E_UNSUPPORTED, "block too large for 32-bit tile offsets");
   const int32_t tile = choose_tile(plan->prec, plan->Mb, plan->N, plan->K);
   hipError_t e = launch_coded_gemm(p, tile, stream);
   if (e != hipSuccess) return hip_fail(e, "coded gemm launch");

@@ -8,9 +8,13 @@
 // A tiles, sums them in FP32 registers and stages the sum in LDS.
 //
 // LDS layout: As[m][k] and Bs[k][n] (both as in global memory, padded by 4
-// floats).  The k index inside a 16-wide chunk is permuted so that lane
-// group q = lane/16 owns k = 4q..4q+3: MFMA t of the chunk contracts
-// k = 4q + t, so each lane fetches its A values with one 128-bit LDS read.
+// floats).  Two index permutations make every LDS fragment read 128 bits
+// wide: (1) inside a 16-wide k chunk, lane group q = lane/16 owns
+// k = 4q..4q+3 and MFMA t of the chunk contracts k = 4q + t, so a lane reads
+// its four A values along k at once; (2) the wave's N range is split so that
+// MFMA column c16 of subtile j is output column 4*c16 + j, so a lane reads
+// the B values of its four subtiles along n at once, and in the epilogue it
+// owns four adjacent output columns (one float4 store per row).
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -34,12 +38,13 @@ struct F32Tile {
   static constexpr int A_SIZE = BM * LDA_S;
   static constexpr int B_SIZE = BK * LDB_S;
   static_assert(A_F4 >= 1 && B_F4 >= 1, "tile too small for 256 threads");
+  static_assert(FN % 4 == 0, "wave N tile must hold 4 interleaved 16-column subtiles");
 };
 
 __device__ __forceinline__ int xcd_remap(int lin, int total) {
   // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
-  // contiguous range of tiles so that tiles sharing A and B panels share an
-  // L2.
+  // contiguous range of tile indices so that tiles sharing A and B panels
+  // share an L2.
   if ((total & 7) != 0) return lin;
   return (lin & 7) * (total >> 3) + (lin >> 3);
 }
@@ -73,87 +78,117 @@ __global__ __launch_bounds__(kThreads, 2) void coded_gemm_f32_kernel(GemmParams 
 
   const int64_t K = p.K, N = p.N, Mb = p.Mb, M = p.M;
 
-  // Per-thread A rows / k offsets, B k-rows / n offsets.
-  int a_row[T::A_F4], a_kc[T::A_F4];
+  // The next K-slice is staged in two halves, one per 16-wide k chunk of the
+  // current slice: half h covers A rows [h*BM/2, (h+1)*BM/2) and B k-rows
+  // [h*BK/2, (h+1)*BK/2).  Its global loads are issued before chunk h's MFMAs
+  // and summed / stored to the other LDS buffer after them, which keeps only
+  // half a slice of prefetch in registers.
+  constexpr int AH = T::A_F4 / 2, BH = T::B_F4 / 2;
+  static_assert(BK == 32 && AH >= 1 && BH >= 1, "two 16-wide chunks per slice");
+  // Per-thread, member-independent offsets (32-bit: the host guarantees
+  // Mb*lda and BK*ldb + N fit).
+  int a_row[T::A_F4], a_kc[T::A_F4], a_off[T::A_F4];
 #pragma unroll
   for (int i = 0; i < T::A_F4; ++i) {
+    // element i of half h = i / AH: rows of half h are contiguous
     const int f = tid + kThreads * i;
     a_row[i] = f / (BK / 4);
     a_kc[i] = (f % (BK / 4)) * 4;
+    a_off[i] = (m0 + a_row[i]) * (int)p.lda + a_kc[i];
   }
-  int b_kr[T::B_F4], b_nc[T::B_F4];
+  int b_kr[T::B_F4], b_nc[T::B_F4], b_off[T::B_F4];
 #pragma unroll
   for (int i = 0; i < T::B_F4; ++i) {
     const int f = tid + kThreads * i;
     b_kr[i] = f / (BN / 4);
     b_nc[i] = (f % (BN / 4)) * 4;
+    b_off[i] = b_kr[i] * (int)p.ldb + n0 + b_nc[i];
   }
+  // Member block bases (uniform).  A tile is "row-full" when every member's
+  // rows m0 .. m0+BM-1 exist, "col-full" when columns n0 .. n0+BN-1 exist.
+  const float* mbase[kPre];
+#pragma unroll
+  for (int m = 0; m < kPre; ++m)
+    mbase[m] = p.A + (m < deg ? (int64_t)ids[m] * Mb * p.lda : 0);
+  const int64_t s_last = deg > 0 ? ids[deg - 1] : 0;  // ids ascending
+  const bool rows_full = m0 + BM <= Mb && s_last * Mb + m0 + BM <= M;
+  const bool cols_full = n0 + BN <= N;
 
-  // Row bases of the (first kPre) member blocks: -1 marks an invalid row.
-  auto a_rowptr = [&](int member, int i) -> const float* {
-    const int64_t s = ids[member];
+  auto a_valid = [&](int member, int i) -> bool {
     const int64_t rb = m0 + a_row[i];
-    const int64_t grow = s * Mb + rb;
-    if (rb >= Mb || grow >= M) return nullptr;
-    return p.A + grow * p.lda;
+    return rb < Mb && (int64_t)ids[member] * Mb + rb < M;
   };
 
-  v4f pre[kPre][T::A_F4];
-  v4f bre[T::B_F4];
+  v4f pre[kPre][AH];
+  v4f bre[BH];
 
-  auto load_a_pre = [&](int k0) {
+  auto load_half = [&](int h, int k0) {
+    if (rows_full && k0 + BK <= K) {
 #pragma unroll
-    for (int mbr = 0; mbr < kPre; ++mbr) {
+      for (int mbr = 0; mbr < kPre; ++mbr)
 #pragma unroll
-      for (int i = 0; i < T::A_F4; ++i) {
+        for (int u = 0; u < AH; ++u)
+          pre[mbr][u] = mbr < deg
+                            ? *reinterpret_cast<const v4f*>(mbase[mbr] + a_off[h * AH + u] + k0)
+                            : v4f{0.f, 0.f, 0.f, 0.f};
+    } else {
+#pragma unroll
+      for (int mbr = 0; mbr < kPre; ++mbr)
+#pragma unroll
+        for (int u = 0; u < AH; ++u) {
+          const int i = h * AH + u;
+          v4f v = {0.f, 0.f, 0.f, 0.f};
+          if (mbr < deg && a_valid(mbr, i) && k0 + a_kc[i] < K)
+            v = *reinterpret_cast<const v4f*>(mbase[mbr] + a_off[i] + k0);
+          pre[mbr][u] = v;
+        }
+    }
+    const float* Bk = p.B + (int64_t)k0 * p.ldb;
+    if (cols_full && k0 + BK <= K) {
+#pragma unroll
+      for (int u = 0; u < BH; ++u) bre[u] = *reinterpret_cast<const v4f*>(Bk + b_off[h * BH + u]);
+    } else {
+#pragma unroll
+      for (int u = 0; u < BH; ++u) {
+        const int i = h * BH + u;
         v4f v = {0.f, 0.f, 0.f, 0.f};
-        if (mbr < deg) {
-          const float* r = a_rowptr(mbr, i);
-          const int64_t kk = k0 + a_kc[i];
-          if (r && kk < K) v = *reinterpret_cast<const v4f*>(r + kk);
+        const int64_t nn = n0 + b_nc[i];
+        if (k0 + b_kr[i] < K) {
+          const float* r = Bk + b_off[i];
+          if (nn + 3 < N) {
+            v = *reinterpret_cast<const v4f*>(r);
+          } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              if (nn + e < N) v[e] = r[e];
+          }
         }
-        pre[mbr][i] = v;
+        bre[u] = v;
       }
     }
   };
-  auto load_b = [&](int k0) {
-#pragma unroll
-    for (int i = 0; i < T::B_F4; ++i) {
-      v4f v = {0.f, 0.f, 0.f, 0.f};
-      const int64_t kk = k0 + b_kr[i];
-      const int64_t nn = n0 + b_nc[i];
-      if (kk < K) {
-        const float* r = p.B + kk * p.ldb + nn;
-        if (nn + 3 < N) {
-          v = *reinterpret_cast<const v4f*>(r);
-        } else {
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-            if (nn + e < N) v[e] = r[e];
-        }
-      }
-      bre[i] = v;
-    }
-  };
-  auto store_tiles = [&](int buf, int k0) {
+  auto store_half = [&](int h, int buf, int k0) {
     float* As = As0 + buf * T::A_SIZE;
     float* Bs = Bs0 + buf * T::B_SIZE;
 #pragma unroll
-    for (int i = 0; i < T::A_F4; ++i) {
-      v4f sum = pre[0][i];
+    for (int u = 0; u < AH; ++u) {
+      const int i = h * AH + u;
+      v4f sum = pre[0][u];
 #pragma unroll
-      for (int mbr = 1; mbr < kPre; ++mbr) sum += pre[mbr][i];
+      for (int mbr = 1; mbr < kPre; ++mbr) sum += pre[mbr][u];
       // members beyond the prefetch depth (high-degree symbols)
       for (int mbr = kPre; mbr < deg; ++mbr) {
-        const float* r = a_rowptr(mbr, i);
-        const int64_t kk = k0 + a_kc[i];
-        if (r && kk < K) sum += *reinterpret_cast<const v4f*>(r + kk);
+        if (a_valid(mbr, i) && k0 + a_kc[i] < K)
+          sum += *reinterpret_cast<const v4f*>(p.A + (int64_t)ids[mbr] * Mb * p.lda + a_off[i] +
+                                               k0);
       }
       *reinterpret_cast<v4f*>(As + a_row[i] * T::LDA_S + a_kc[i]) = sum;
     }
 #pragma unroll
-    for (int i = 0; i < T::B_F4; ++i)
-      *reinterpret_cast<v4f*>(Bs + b_kr[i] * T::LDB_S + b_nc[i]) = bre[i];
+    for (int u = 0; u < BH; ++u) {
+      const int i = h * BH + u;
+      *reinterpret_cast<v4f*>(Bs + b_kr[i] * T::LDB_S + b_nc[i]) = bre[u];
+    }
   };
 
   v4f acc[T::FM][T::FN];
@@ -162,47 +197,53 @@ __global__ __launch_bounds__(kThreads, 2) void coded_gemm_f32_kernel(GemmParams 
 #pragma unroll
     for (int j = 0; j < T::FN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
+  auto compute_chunk = [&](const float* As, const float* Bs, int kk) {
+    v4f a[T::FM];
+    v4f b[T::FN / 4][4];
+#pragma unroll
+    for (int i = 0; i < T::FM; ++i)
+      a[i] = *reinterpret_cast<const v4f*>(As + (wm * T::TM + i * 16 + c16) * T::LDA_S + kk +
+                                           4 * q);
+#pragma unroll
+    for (int jg = 0; jg < T::FN / 4; ++jg)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        b[jg][t] = *reinterpret_cast<const v4f*>(Bs + (kk + 4 * q + t) * T::LDB_S + wn * T::TN +
+                                                 jg * 64 + 4 * c16);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+        for (int j = 0; j < T::FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][t], b[j / 4][t][j % 4],
+                                                           acc[i][j], 0, 0, 0);
+  };
+
   const int nk = (int)((K + BK - 1) / BK);
-  load_a_pre(0);
-  load_b(0);
-  store_tiles(0, 0);
+  load_half(0, 0);
+  store_half(0, 0, 0);
+  load_half(1, 0);
+  store_half(1, 0, 0);
   __syncthreads();
 
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
     const bool more = kt + 1 < nk;
-    if (more) {
-      load_a_pre((kt + 1) * BK);
-      load_b((kt + 1) * BK);
-    }
+    const int kn = (kt + 1) * BK;
     const float* As = As0 + buf * T::A_SIZE;
     const float* Bs = Bs0 + buf * T::B_SIZE;
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 16) {
-      v4f a[T::FM];
-      v4f b[T::FN];
-#pragma unroll
-      for (int i = 0; i < T::FM; ++i)
-        a[i] = *reinterpret_cast<const v4f*>(As + (wm * T::TM + i * 16 + c16) * T::LDA_S + kk +
-                                             4 * q);
-#pragma unroll
-      for (int j = 0; j < T::FN; ++j)
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-          b[j][t] = Bs[(kk + 4 * q + t) * T::LDB_S + wn * T::TN + j * 16 + c16];
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int i = 0; i < T::FM; ++i)
-#pragma unroll
-          for (int j = 0; j < T::FN; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][t], b[j][t], acc[i][j], 0, 0, 0);
+    for (int h = 0; h < 2; ++h) {
+      if (more) load_half(h, kn);
+      compute_chunk(As, Bs, h * 16);
+      if (more) store_half(h, buf ^ 1, kn);
     }
-    if (more) store_tiles(buf ^ 1, (kt + 1) * BK);
     __syncthreads();
   }
 
-  // Epilogue: lane holds rows 4q..4q+3 of column c16 of each 16x16 subtile.
+  // Epilogue: for subtile (i, j) the lane holds rows 4q..4q+3; subtiles
+  // j = 4*jg .. 4*jg+3 are the adjacent columns 64*jg + 4*c16 + 0..3.
   float* out;
   int64_t ldo, rows;
   if (dest >= 0) {
@@ -215,18 +256,28 @@ __global__ __launch_bounds__(kThreads, 2) void coded_gemm_f32_kernel(GemmParams 
     ldo = p.ldc;
     rows = M - s * Mb < Mb ? M - s * Mb : Mb;
   }
+  const bool vec_ok = (ldo & 3) == 0;
 #pragma unroll
-  for (int i = 0; i < T::FM; ++i)
+  for (int jg = 0; jg < T::FN / 4; ++jg) {
+    const int64_t col = n0 + wn * T::TN + jg * 64 + 4 * c16;
 #pragma unroll
-    for (int j = 0; j < T::FN; ++j) {
-      const int64_t col = n0 + wn * T::TN + j * 16 + c16;
-      if (col >= N) continue;
+    for (int i = 0; i < T::FM; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t row = m0 + wm * T::TM + i * 16 + 4 * q + r;
-        if (row < rows) out[row * ldo + col] = acc[i][j][r];
+        if (row >= rows) continue;
+        float* dst = out + row * ldo + col;
+        const v4f v = {acc[i][4 * jg + 0][r], acc[i][4 * jg + 1][r], acc[i][4 * jg + 2][r],
+                       acc[i][4 * jg + 3][r]};
+        if (col + 3 < N && vec_ok) {
+          *reinterpret_cast<v4f*>(dst) = v;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (col + e < N) dst[e] = v[e];
+        }
       }
-    }
+  }
 }
 
 struct TileEntry {
@@ -236,9 +287,9 @@ struct TileEntry {
 
 const TileEntry kTiles[] = {
     {{128, 128, 32}, coded_gemm_f32_kernel<128, 128, 32>},
-    {{64, 64, 32}, coded_gemm_f32_kernel<64, 64, 32>},
-    {{128, 64, 32}, coded_gemm_f32_kernel<128, 64, 32>},
     {{64, 128, 32}, coded_gemm_f32_kernel<64, 128, 32>},
+    {{128, 256, 32}, coded_gemm_f32_kernel<128, 256, 32>},
+    {{256, 128, 32}, coded_gemm_f32_kernel<256, 128, 32>},
 };
 
 }  // namespace
