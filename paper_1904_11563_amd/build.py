@@ -16,8 +16,10 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbpx.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-# Packed FP32 instructions are kept out of the device code.
+# Packed FP32 instructions are kept out of the device code.  The iterative
+# ILP scheduler interleaves LDS reads and MFMAs better in the GEMM loops.
 COMMON = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950",
+          "-mllvm", "-amdgpu-sched-strategy=iterative-ilp",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function"]
 

@@ -17,6 +17,8 @@
 // owns four adjacent output columns (one float4 store per row).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace bpx {
@@ -49,8 +51,8 @@ __device__ __forceinline__ int xcd_remap(int lin, int total) {
   return (lin & 7) * (total >> 3) + (lin >> 3);
 }
 
-template <int BM, int BN, int BK>
-__global__ __launch_bounds__(kThreads, 2) void coded_gemm_f32_kernel(GemmParams p) {
+template <int BM, int BN, int BK, int OCC>
+__global__ __launch_bounds__(kThreads, OCC) void coded_gemm_f32_kernel(GemmParams p) {
   using T = F32Tile<BM, BN, BK>;
   __shared__ __attribute__((aligned(16))) float lds[2 * (T::A_SIZE + T::B_SIZE)];
   float* As0 = lds;
@@ -85,89 +87,94 @@ __global__ __launch_bounds__(kThreads, 2) void coded_gemm_f32_kernel(GemmParams 
   // half a slice of prefetch in registers.
   constexpr int AH = T::A_F4 / 2, BH = T::B_F4 / 2;
   static_assert(BK == 32 && AH >= 1 && BH >= 1, "two 16-wide chunks per slice");
-  // Per-thread, member-independent offsets (32-bit: the host guarantees
-  // Mb*lda and BK*ldb + N fit).
-  int a_row[T::A_F4], a_kc[T::A_F4], a_off[T::A_F4];
+  // Per-thread, member-independent byte offsets (32-bit: the host
+  // guarantees a block of A and a K-slice of B fit in 2^30 floats).
+  int a_row[T::A_F4], a_kc[T::A_F4];
+  uint32_t a_off[T::A_F4];
 #pragma unroll
   for (int i = 0; i < T::A_F4; ++i) {
-    // element i of half h = i / AH: rows of half h are contiguous
     const int f = tid + kThreads * i;
     a_row[i] = f / (BK / 4);
     a_kc[i] = (f % (BK / 4)) * 4;
-    a_off[i] = (m0 + a_row[i]) * (int)p.lda + a_kc[i];
+    a_off[i] = (uint32_t)((m0 + a_row[i]) * (int)p.lda + a_kc[i]) * 4u;
   }
-  int b_kr[T::B_F4], b_nc[T::B_F4], b_off[T::B_F4];
+  int b_kr[T::B_F4], b_nc[T::B_F4];
+  uint32_t b_off[T::B_F4];
 #pragma unroll
   for (int i = 0; i < T::B_F4; ++i) {
     const int f = tid + kThreads * i;
     b_kr[i] = f / (BN / 4);
     b_nc[i] = (f % (BN / 4)) * 4;
-    b_off[i] = b_kr[i] * (int)p.ldb + n0 + b_nc[i];
+    b_off[i] = (uint32_t)(b_kr[i] * (int)p.ldb + n0 + b_nc[i]) * 4u;
   }
-  // Member block bases (uniform).  A tile is "row-full" when every member's
-  // rows m0 .. m0+BM-1 exist, "col-full" when columns n0 .. n0+BN-1 exist.
-  const float* mbase[kPre];
+  // Member block bases (uniform).  A tile is "interior" when every member's
+  // rows m0 .. m0+BM-1 and the columns n0 .. n0+BN-1 exist.
+  const char* mbase[kPre];
 #pragma unroll
   for (int m = 0; m < kPre; ++m)
-    mbase[m] = p.A + (m < deg ? (int64_t)ids[m] * Mb * p.lda : 0);
+    mbase[m] = reinterpret_cast<const char*>(p.A + (m < deg ? (int64_t)ids[m] * Mb * p.lda : 0));
   const int64_t s_last = deg > 0 ? ids[deg - 1] : 0;  // ids ascending
-  const bool rows_full = m0 + BM <= Mb && s_last * Mb + m0 + BM <= M;
-  const bool cols_full = n0 + BN <= N;
+  const bool interior =
+      m0 + BM <= Mb && s_last * Mb + m0 + BM <= M && n0 + BN <= N;
 
-  auto a_valid = [&](int member, int i) -> bool {
+  auto a_valid = [&](int member, int i) __attribute__((always_inline)) -> bool {
     const int64_t rb = m0 + a_row[i];
     return rb < Mb && (int64_t)ids[member] * Mb + rb < M;
+  };
+  auto ld4 = [](const char* base, uint32_t off) __attribute__((always_inline)) -> v4f {
+    return *reinterpret_cast<const v4f*>(base + off);
   };
 
   v4f pre[kPre][AH];
   v4f bre[BH];
 
-  auto load_half = [&](int h, int k0) {
-    if (rows_full && k0 + BK <= K) {
+  // Unpredicated loads of half h of the slice at k0 (interior tiles, full
+  // slices).  Members past deg are not loaded and not summed.
+  auto load_half_full = [&](int h, int k0) __attribute__((always_inline)) {
+    const uint32_t kb4 = (uint32_t)k0 * 4u;
 #pragma unroll
-      for (int mbr = 0; mbr < kPre; ++mbr)
+    for (int mbr = 0; mbr < kPre; ++mbr)
+      if (mbr < deg) {
 #pragma unroll
-        for (int u = 0; u < AH; ++u)
-          pre[mbr][u] = mbr < deg
-                            ? *reinterpret_cast<const v4f*>(mbase[mbr] + a_off[h * AH + u] + k0)
-                            : v4f{0.f, 0.f, 0.f, 0.f};
-    } else {
+        for (int u = 0; u < AH; ++u) pre[mbr][u] = ld4(mbase[mbr], a_off[h * AH + u] + kb4);
+      }
+    const char* Bk = reinterpret_cast<const char*>(p.B + (int64_t)k0 * p.ldb);
 #pragma unroll
-      for (int mbr = 0; mbr < kPre; ++mbr)
+    for (int u = 0; u < BH; ++u) bre[u] = ld4(Bk, b_off[h * BH + u]);
+  };
+  // Predicated loads (edge tiles, ragged last slice).
+  auto load_half_edge = [&](int h, int k0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int mbr = 0; mbr < kPre; ++mbr)
+      if (mbr < deg) {
 #pragma unroll
         for (int u = 0; u < AH; ++u) {
           const int i = h * AH + u;
           v4f v = {0.f, 0.f, 0.f, 0.f};
-          if (mbr < deg && a_valid(mbr, i) && k0 + a_kc[i] < K)
-            v = *reinterpret_cast<const v4f*>(mbase[mbr] + a_off[i] + k0);
+          if (a_valid(mbr, i) && k0 + a_kc[i] < K) v = ld4(mbase[mbr], a_off[i] + k0 * 4u);
           pre[mbr][u] = v;
         }
-    }
-    const float* Bk = p.B + (int64_t)k0 * p.ldb;
-    if (cols_full && k0 + BK <= K) {
-#pragma unroll
-      for (int u = 0; u < BH; ++u) bre[u] = *reinterpret_cast<const v4f*>(Bk + b_off[h * BH + u]);
-    } else {
-#pragma unroll
-      for (int u = 0; u < BH; ++u) {
-        const int i = h * BH + u;
-        v4f v = {0.f, 0.f, 0.f, 0.f};
-        const int64_t nn = n0 + b_nc[i];
-        if (k0 + b_kr[i] < K) {
-          const float* r = Bk + b_off[i];
-          if (nn + 3 < N) {
-            v = *reinterpret_cast<const v4f*>(r);
-          } else {
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-              if (nn + e < N) v[e] = r[e];
-          }
-        }
-        bre[u] = v;
       }
+    const float* Bk = p.B + (int64_t)k0 * p.ldb;
+#pragma unroll
+    for (int u = 0; u < BH; ++u) {
+      const int i = h * BH + u;
+      v4f v = {0.f, 0.f, 0.f, 0.f};
+      const int64_t nn = n0 + b_nc[i];
+      if (k0 + b_kr[i] < K) {
+        const float* r = Bk + b_off[i] / 4u;
+        if (nn + 3 < N) {
+          v = *reinterpret_cast<const v4f*>(r);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (nn + e < N) v[e] = r[e];
+        }
+      }
+      bre[u] = v;
     }
   };
-  auto store_half = [&](int h, int buf, int k0) {
+  auto store_half = [&](int h, int buf, int k0) __attribute__((always_inline)) {
     float* As = As0 + buf * T::A_SIZE;
     float* Bs = Bs0 + buf * T::B_SIZE;
 #pragma unroll
@@ -175,12 +182,13 @@ __global__ __launch_bounds__(kThreads, 2) void coded_gemm_f32_kernel(GemmParams 
       const int i = h * AH + u;
       v4f sum = pre[0][u];
 #pragma unroll
-      for (int mbr = 1; mbr < kPre; ++mbr) sum += pre[mbr][u];
+      for (int mbr = 1; mbr < kPre; ++mbr)
+        if (mbr < deg) sum += pre[mbr][u];
       // members beyond the prefetch depth (high-degree symbols)
       for (int mbr = kPre; mbr < deg; ++mbr) {
         if (a_valid(mbr, i) && k0 + a_kc[i] < K)
-          sum += *reinterpret_cast<const v4f*>(p.A + (int64_t)ids[mbr] * Mb * p.lda + a_off[i] +
-                                               k0);
+          sum += *reinterpret_cast<const v4f*>(p.A + (int64_t)ids[mbr] * Mb * p.lda +
+                                               a_off[i] / 4u + k0);
       }
       *reinterpret_cast<v4f*>(As + a_row[i] * T::LDA_S + a_kc[i]) = sum;
     }
@@ -197,7 +205,7 @@ __global__ __launch_bounds__(kThreads, 2) void coded_gemm_f32_kernel(GemmParams 
 #pragma unroll
     for (int j = 0; j < T::FN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
-  auto compute_chunk = [&](const float* As, const float* Bs, int kk) {
+  auto compute_chunk = [&](const float* As, const float* Bs, int kk) __attribute__((always_inline)) {
     v4f a[T::FM];
     v4f b[T::FN / 4][4];
 #pragma unroll
@@ -220,27 +228,49 @@ __global__ __launch_bounds__(kThreads, 2) void coded_gemm_f32_kernel(GemmParams 
                                                            acc[i][j], 0, 0, 0);
   };
 
-  const int nk = (int)((K + BK - 1) / BK);
-  load_half(0, 0);
-  store_half(0, 0, 0);
-  load_half(1, 0);
-  store_half(1, 0, 0);
-  __syncthreads();
-
-  for (int kt = 0; kt < nk; ++kt) {
+  // One K-slice: compute slice kt from LDS, staging slice kt+1 (if any) into
+  // the other buffer with full or predicated loads.
+  auto slice = [&](int kt, bool more, auto full) __attribute__((always_inline)) {
     const int buf = kt & 1;
-    const bool more = kt + 1 < nk;
     const int kn = (kt + 1) * BK;
     const float* As = As0 + buf * T::A_SIZE;
     const float* Bs = Bs0 + buf * T::B_SIZE;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      if (more) load_half(h, kn);
+      if (more) {
+        if constexpr (decltype(full)::value)
+          load_half_full(h, kn);
+        else
+          load_half_edge(h, kn);
+      }
       compute_chunk(As, Bs, h * 16);
       if (more) store_half(h, buf ^ 1, kn);
     }
     __syncthreads();
+  };
+  using Full = std::integral_constant<bool, true>;
+  using Edge = std::integral_constant<bool, false>;
+
+  const int nk = (int)((K + BK - 1) / BK);
+  const int nk_full = (int)(K / BK);
+  if (interior && nk_full >= 1) {
+    load_half_full(0, 0);
+    store_half(0, 0, 0);
+    load_half_full(1, 0);
+    store_half(1, 0, 0);
+  } else {
+    load_half_edge(0, 0);
+    store_half(0, 0, 0);
+    load_half_edge(1, 0);
+    store_half(1, 0, 0);
   }
+  __syncthreads();
+  int kt = 0;
+  if (interior) {
+    // steady state: slice kt+1 is a full slice
+    for (; kt + 1 < nk_full; ++kt) slice(kt, true, Full{});
+  }
+  for (; kt < nk; ++kt) slice(kt, kt + 1 < nk, Edge{});
 
   // Epilogue: for subtile (i, j) the lane holds rows 4q..4q+3; subtiles
   // j = 4*jg .. 4*jg+3 are the adjacent columns 64*jg + 4*c16 + 0..3.
@@ -286,10 +316,11 @@ struct TileEntry {
 };
 
 const TileEntry kTiles[] = {
-    {{128, 128, 32}, coded_gemm_f32_kernel<128, 128, 32>},
-    {{64, 128, 32}, coded_gemm_f32_kernel<64, 128, 32>},
-    {{128, 256, 32}, coded_gemm_f32_kernel<128, 256, 32>},
-    {{256, 128, 32}, coded_gemm_f32_kernel<256, 128, 32>},
+    {{128, 128, 32}, coded_gemm_f32_kernel<128, 128, 32, 2>},
+    {{64, 128, 32}, coded_gemm_f32_kernel<64, 128, 32, 2>},
+    {{128, 256, 32}, coded_gemm_f32_kernel<128, 256, 32, 1>},
+    {{256, 128, 32}, coded_gemm_f32_kernel<256, 128, 32, 1>},
+    {{256, 256, 32}, coded_gemm_f32_kernel<256, 256, 32, 1>},
 };
 
 }  // namespace
