@@ -44,14 +44,20 @@ int32_t log2_bucket(int64_t x) {
   return b;
 }
 
+int32_t tile_count_for(int32_t prec) {
+  return (prec == BPX_PREC_BF16 || prec == BPX_PREC_BF16X3) ? bf16_tile_count()
+                                                              : gemm_tile_count();
+}
+
 int32_t choose_tile(int32_t prec, int64_t Mb, int64_t N, int64_t K) {
-  if (g_force_tile >= 0) return g_force_tile;
+  if (g_force_tile >= 0 && g_force_tile < tile_count_for(prec)) return g_force_tile;
   if (g_tile_table_set) {
     const int32_t idx =
         ((prec * 8 + log2_bucket(Mb)) * 8 + log2_bucket(N)) * 8 + log2_bucket(K);
     const int32_t t = g_tile_table[idx];
-    if (t >= 0 && t < gemm_tile_count()) return t;
+    if (t >= 0 && t < tile_count_for(prec)) return t;
   }
+  if (prec == BPX_PREC_BF16 || prec == BPX_PREC_BF16X3) return 1;  // 64x128, no spills
   // default: 64x128 (three workgroups per CU) measured fastest for the FP32
   // products on 8192x8192x4096 and for small blocks
   (void)Mb;
@@ -102,7 +108,8 @@ bpx_status check_device_call(bpx_plan* plan) {
   if (!plan) return fail(BPX_E_INVALID, "null plan");
   if (!plan->decodable) return fail(BPX_E_UNDECODABLE, "plan is not decodable");
   if (plan->K % 4 != 0) return fail(BPX_E_INVALID, "K must be a multiple of 4");
-  if (plan->prec != BPX_PREC_F32)
+  if (plan->prec != BPX_PREC_F32 && plan->prec != BPX_PREC_BF16 &&
+      plan->prec != BPX_PREC_BF16X3)
     return fail(BPX_E_UNSUPPORTED, "precision not built into this library");
   return upload(plan);
 }
@@ -122,8 +129,8 @@ bpx_status gemm_impl(bpx_plan* plan, const float* A, int64_t lda, const float* B
   if ((st = check_matrix(A, lda, plan->K, "A")) != BPX_OK) return st;
   if ((st = check_matrix(B, ldb, plan->N, "B")) != BPX_OK) return st;
   if ((st = check_matrix(C, ldc, plan->N, "C")) != BPX_OK) return st;
-  if (plan->y_bytes() > 0 && (!ws || ws_bytes < plan->y_bytes() || !aligned16(ws)))
-    return fail(BPX_E_INVALID, "workspace missing, misaligned or too small");
+  if (plan->ws_bytes() > 0 && (!ws || ws_bytes < plan->ws_bytes() || ((uintptr_t)ws & 255u)))
+    return fail(BPX_E_INVALID, "workspace missing, not 256-byte aligned or too small");
   GemmParams p{};
   p.A = A;
   p.lda = lda;
@@ -145,7 +152,20 @@ bpx_status gemm_impl(bpx_plan* plan, const float* A, int64_t lda, const float* B
   if ((plan->Mb + 256) * lda >= ((int64_t)1 << 30) || 64 * ldb + plan->N >= ((int64_t)1 << 30))
     return fail(BPX_E_UNSUPPORTED, "block too large for 32-bit tile offsets");
   const int32_t tile = choose_tile(plan->prec, plan->Mb, plan->N, plan->K);
-  hipError_t e = launch_coded_gemm(p, tile, stream);
+  hipError_t e;
+  if (plan->prec == BPX_PREC_BF16 || plan->prec == BPX_PREC_BF16X3) {
+    char* planes = static_cast<char*>(ws) + bpx_plan::align256(plan->y_bytes());
+    void* hi = planes;
+    void* lo = plan->prec == BPX_PREC_BF16X3 ? planes + plan->bt_plane_bytes() : nullptr;
+    p.bt_hi = static_cast<const unsigned short*>(hi);
+    p.bt_lo = static_cast<const unsigned short*>(lo);
+    p.kp = plan->kp();
+    e = launch_split_b(B, ldb, plan->K, plan->N, plan->kp(), hi, lo, stream);
+    if (e != hipSuccess) return hip_fail(e, "split-B launch");
+    e = launch_coded_gemm_bf16(p, tile, stream);
+  } else {
+    e = launch_coded_gemm(p, tile, stream);
+  }
   if (e != hipSuccess) return hip_fail(e, "coded gemm launch");
   return BPX_OK;
 }
@@ -154,8 +174,8 @@ bpx_status peel_impl(bpx_plan* plan, const void* ws, size_t ws_bytes, float* C, 
                      hipStream_t stream) {
   bpx_status st;
   if ((st = check_matrix(C, ldc, plan->N, "C")) != BPX_OK) return st;
-  if (plan->y_bytes() > 0 && (!ws || ws_bytes < plan->y_bytes() || !aligned16(ws)))
-    return fail(BPX_E_INVALID, "workspace missing, misaligned or too small");
+  if (plan->y_bytes() > 0 && (!ws || ws_bytes < plan->y_bytes() || ((uintptr_t)ws & 255u)))
+    return fail(BPX_E_INVALID, "workspace missing, not 256-byte aligned or too small");
   PeelParams p{};
   p.Y = static_cast<const float*>(ws);
   p.C = C;
@@ -302,7 +322,7 @@ bpx_status bpx_plan_schedule(const bpx_plan* plan, const int32_t** computed, con
 bpx_status bpx_plan_workspace_bytes(const bpx_plan* plan, size_t* ws_bytes,
                                     size_t* encode_bytes) {
   if (!plan) return fail(BPX_E_INVALID, "null plan");
-  if (ws_bytes) *ws_bytes = plan->y_bytes();
+  if (ws_bytes) *ws_bytes = plan->ws_bytes();
   if (encode_bytes)
     *encode_bytes = plan->computed.size() * (size_t)plan->Mb * (size_t)plan->K * sizeof(float);
   return BPX_OK;
@@ -399,7 +419,8 @@ bpx_status bpx_set_tile_table(const int32_t* table, int32_t n_entries) {
 }
 
 bpx_status bpx_force_tile(int32_t tile) {
-  if (tile >= gemm_tile_count()) return fail(BPX_E_INVALID, "no such tile shape");
+  if (tile >= std::max(gemm_tile_count(), bf16_tile_count()))
+    return fail(BPX_E_INVALID, "no such tile shape");
   g_force_tile = tile < 0 ? -1 : tile;
   return BPX_OK;
 }

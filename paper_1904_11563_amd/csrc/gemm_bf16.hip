@@ -1,0 +1,353 @@
+// Coded GEMM in BF16 and split-BF16x3 on MFMA (v_mfma_f32_16x16x32_bf16),
+// FP32 accumulation, encode fused into the A-operand load.
+//
+// The coded block C_g = sum of its data blocks A_s (Sec. II, XOR read as a
+// real sum) is summed in FP32 registers while the A tile is staged, then
+// rounded to BF16 (round to nearest even): hi = bf16(x), lo = bf16(x - hi).
+// B is split the same way once per call by split_b_kernel into transposed
+// planes Bt_hi, Bt_lo (N x Kp, k contiguous, zero past K) in the workspace.
+//   BF16:   Y += A_hi . B_hi
+//   BF16x3: Y += A_lo . B_hi + A_hi . B_lo + A_hi . B_hi, the two small
+//           products of each 32-wide k step accumulated first.
+//
+// MFMA operands: lane (q = lane/16, c = lane%16) supplies row c of A and
+// column c of B, eight consecutive k values each (k = 8q .. 8q+7 of the
+// step); the same k assignment on both sides makes the contraction exact
+// whatever order the unit sums in.  Output columns are interleaved as in
+// the FP32 kernel (subtile j, column c -> 4c + j) for float4 stores.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "kernels.hpp"
+
+namespace bpx {
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
+typedef unsigned short us;
+
+constexpr int kThreads = 256;
+constexpr int kPre = 4;
+constexpr int BK = 32;
+constexpr int KS = BK + 8;  // LDS row stride in bf16 (80 bytes)
+
+__device__ __forceinline__ v4bf to_bf16(v4f x) {
+  v4bf r;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) r[e] = (__bf16)x[e];
+  return r;
+}
+__device__ __forceinline__ v4f from_bf16(v4bf x) {
+  v4f r;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) r[e] = (float)x[e];
+  return r;
+}
+
+// ------------------------------------------------------------- B split ---
+// Bt_hi[n][k] = bf16(B[k][n]); Bt_lo[n][k] = bf16(B[k][n] - Bt_hi[n][k]);
+// k in [K, Kp) is zero.  64 x 64 tiles transposed through LDS.
+__global__ __launch_bounds__(256) void split_b_kernel(const float* B, int64_t ldb, int64_t K,
+                                                      int64_t N, int64_t Kp, us* bt_hi, us* bt_lo) {
+  __shared__ float t[64][65];
+  const int64_t k0 = (int64_t)blockIdx.y * 64, n0 = (int64_t)blockIdx.x * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4) {
+    const int64_t k = k0 + r, n = n0 + tx;
+    t[r][tx] = (k < K && n < N) ? B[k * ldb + n] : 0.f;
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {
+    const int64_t n = n0 + r, k = k0 + tx;
+    if (n < N && k < Kp) {
+      const float x = t[tx][r];
+      const __bf16 h = (__bf16)x;
+      const __bf16 l = (__bf16)(x - (float)h);
+      bt_hi[n * Kp + k] = __builtin_bit_cast(us, h);
+      if (bt_lo) bt_lo[n * Kp + k] = __builtin_bit_cast(us, l);
+    }
+  }
+}
+
+// -------------------------------------------------------------- GEMM ---
+template <int BM, int BN>
+struct Bf16Tile {
+  static constexpr int TM = BM / 2, TN = BN / 2;
+  static constexpr int FM = TM / 16, FN = TN / 16;
+  static constexpr int A_F4 = BM * BK / 4 / kThreads;     // fp32 float4 per thread
+  static constexpr int B_CH = BN * BK * 2 / 16 / kThreads;  // 16-byte chunks per plane
+  static constexpr int A_PLANE = BM * KS;                   // bf16 elements
+  static constexpr int B_PLANE = BN * KS;
+  static_assert(A_F4 >= 1 && B_CH >= 1 && FN % 4 == 0, "tile shape");
+};
+
+__device__ __forceinline__ int xcd_remap(int lin, int total) {
+  if ((total & 7) != 0) return lin;
+  return (lin & 7) * (total >> 3) + (lin >> 3);
+}
+
+template <int BM, int BN, int SPLIT>
+__device__ __forceinline__ void bf16_tile(const GemmParams& p, int si, int mt, int nt,
+                                          us* lds) {
+  using T = Bf16Tile<BM, BN>;
+  constexpr int NPL = SPLIT == 3 ? 2 : 1;  // planes per operand
+  constexpr int STAGE = NPL * (T::A_PLANE + T::B_PLANE);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int q = lane >> 4, c16 = lane & 15;
+  const int m0 = mt * BM, n0 = nt * BN;
+
+  const int id_off = p.syms[4 * si + 0];
+  const int deg = p.syms[4 * si + 1];
+  const int dest = p.syms[4 * si + 2];
+  const int32_t* ids = p.ids + id_off;
+  const int64_t K = p.K, N = p.N, Mb = p.Mb, M = p.M, Kp = p.kp;
+
+  int a_row[T::A_F4], a_kc[T::A_F4];
+  uint32_t a_off[T::A_F4];
+#pragma unroll
+  for (int i = 0; i < T::A_F4; ++i) {
+    const int f = tid + kThreads * i;
+    a_row[i] = f / (BK / 4);
+    a_kc[i] = (f % (BK / 4)) * 4;
+    a_off[i] = (uint32_t)((m0 + a_row[i]) * (int)p.lda + a_kc[i]) * 4u;
+  }
+  // B chunks: chunk f -> row n = f / 4 of the tile, k offset (f % 4) * 8
+  int b_n[T::B_CH], b_kc[T::B_CH];
+#pragma unroll
+  for (int i = 0; i < T::B_CH; ++i) {
+    const int f = tid + kThreads * i;
+    b_n[i] = f / 4;
+    b_kc[i] = (f % 4) * 8;
+  }
+  const char* mbase[kPre];
+#pragma unroll
+  for (int m = 0; m < kPre; ++m)
+    mbase[m] = reinterpret_cast<const char*>(p.A + (m < deg ? (int64_t)ids[m] * Mb * p.lda : 0));
+  const int64_t s_last = deg > 0 ? ids[deg - 1] : 0;
+  const bool rows_full = m0 + BM <= Mb && s_last * Mb + m0 + BM <= M;
+
+  auto a_valid = [&](int member, int i) __attribute__((always_inline)) -> bool {
+    const int64_t rb = m0 + a_row[i];
+    return rb < Mb && (int64_t)ids[member] * Mb + rb < M;
+  };
+
+  v4f pre[kPre][T::A_F4];
+  uint4 bre[NPL][T::B_CH];
+
+  auto load = [&](int k0) __attribute__((always_inline)) {
+    if (rows_full && k0 + BK <= K) {
+#pragma unroll
+      for (int mbr = 0; mbr < kPre; ++mbr)
+        if (mbr < deg) {
+#pragma unroll
+          for (int i = 0; i < T::A_F4; ++i)
+            pre[mbr][i] = *reinterpret_cast<const v4f*>(mbase[mbr] + a_off[i] + k0 * 4u);
+        }
+    } else {
+#pragma unroll
+      for (int mbr = 0; mbr < kPre; ++mbr)
+        if (mbr < deg) {
+#pragma unroll
+          for (int i = 0; i < T::A_F4; ++i) {
+            v4f v = {0.f, 0.f, 0.f, 0.f};
+            if (a_valid(mbr, i) && k0 + a_kc[i] < K)
+              v = *reinterpret_cast<const v4f*>(mbase[mbr] + a_off[i] + k0 * 4u);
+            pre[mbr][i] = v;
+          }
+        }
+    }
+#pragma unroll
+    for (int pl = 0; pl < NPL; ++pl) {
+      const us* bt = pl == 0 ? p.bt_hi : p.bt_lo;
+#pragma unroll
+      for (int i = 0; i < T::B_CH; ++i) {
+        const int64_t n = n0 + b_n[i];
+        uint4 v = {0u, 0u, 0u, 0u};
+        if (n < N) v = *reinterpret_cast<const uint4*>(bt + n * Kp + k0 + b_kc[i]);
+        bre[pl][i] = v;
+      }
+    }
+  };
+  auto store = [&](int buf, int k0) __attribute__((always_inline)) {
+    us* st = lds + buf * STAGE;
+    us* As_hi = st;
+    us* As_lo = st + T::A_PLANE;
+    us* Bs = st + NPL * T::A_PLANE;
+#pragma unroll
+    for (int i = 0; i < T::A_F4; ++i) {
+      v4f sum = pre[0][i];
+#pragma unroll
+      for (int mbr = 1; mbr < kPre; ++mbr)
+        if (mbr < deg) sum += pre[mbr][i];
+      for (int mbr = kPre; mbr < deg; ++mbr) {
+        if (a_valid(mbr, i) && k0 + a_kc[i] < K)
+          sum += *reinterpret_cast<const v4f*>(p.A + (int64_t)ids[mbr] * Mb * p.lda +
+                                               a_off[i] / 4u + k0);
+      }
+      const v4bf hi = to_bf16(sum);
+      *reinterpret_cast<v4bf*>(As_hi + a_row[i] * KS + a_kc[i]) = hi;
+      if (SPLIT == 3)
+        *reinterpret_cast<v4bf*>(As_lo + a_row[i] * KS + a_kc[i]) = to_bf16(sum - from_bf16(hi));
+    }
+#pragma unroll
+    for (int pl = 0; pl < NPL; ++pl)
+#pragma unroll
+      for (int i = 0; i < T::B_CH; ++i)
+        *reinterpret_cast<uint4*>(Bs + pl * T::B_PLANE + b_n[i] * KS + b_kc[i]) = bre[pl][i];
+  };
+
+  v4f acc[T::FM][T::FN];
+#pragma unroll
+  for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < T::FN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  auto compute = [&](int buf) __attribute__((always_inline)) {
+    const us* st = lds + buf * STAGE;
+    const us* As_hi = st;
+    const us* As_lo = st + T::A_PLANE;
+    const us* Bs_hi = st + NPL * T::A_PLANE;
+    const us* Bs_lo = Bs_hi + T::B_PLANE;
+    v8bf ah[T::FM], al[T::FM], bh[T::FN], bl[T::FN];
+#pragma unroll
+    for (int i = 0; i < T::FM; ++i) {
+      const int r = wm * T::TM + i * 16 + c16;
+      ah[i] = *reinterpret_cast<const v8bf*>(As_hi + r * KS + 8 * q);
+      if (SPLIT == 3) al[i] = *reinterpret_cast<const v8bf*>(As_lo + r * KS + 8 * q);
+    }
+#pragma unroll
+    for (int j = 0; j < T::FN; ++j) {
+      const int n = wn * T::TN + (j / 4) * 64 + 4 * c16 + (j % 4);
+      bh[j] = *reinterpret_cast<const v8bf*>(Bs_hi + n * KS + 8 * q);
+      if (SPLIT == 3) bl[j] = *reinterpret_cast<const v8bf*>(Bs_lo + n * KS + 8 * q);
+    }
+    if (SPLIT == 3) {
+#pragma unroll
+      for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+        for (int j = 0; j < T::FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+        for (int j = 0; j < T::FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+      for (int j = 0; j < T::FN; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+  };
+
+  const int nk = (int)((K + BK - 1) / BK);
+  load(0);
+  store(0, 0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const bool more = kt + 1 < nk;
+    if (more) load((kt + 1) * BK);
+    compute(kt & 1);
+    if (more) store((kt + 1) & 1, (kt + 1) * BK);
+    __syncthreads();
+  }
+
+  float* out;
+  int64_t ldo, rows;
+  if (dest >= 0) {
+    out = p.Y + (int64_t)dest * Mb * N;
+    ldo = N;
+    rows = Mb;
+  } else {
+    const int64_t s = -1 - dest;
+    out = p.C + s * Mb * p.ldc;
+    ldo = p.ldc;
+    rows = M - s * Mb < Mb ? M - s * Mb : Mb;
+  }
+  const bool vec_ok = (ldo & 3) == 0;
+#pragma unroll
+  for (int jg = 0; jg < T::FN / 4; ++jg) {
+    const int64_t col = n0 + wn * T::TN + jg * 64 + 4 * c16;
+#pragma unroll
+    for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = m0 + wm * T::TM + i * 16 + 4 * q + r;
+        if (row >= rows) continue;
+        float* dst = out + row * ldo + col;
+        const v4f v = {acc[i][4 * jg + 0][r], acc[i][4 * jg + 1][r], acc[i][4 * jg + 2][r],
+                       acc[i][4 * jg + 3][r]};
+        if (col + 3 < N && vec_ok) {
+          *reinterpret_cast<v4f*>(dst) = v;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (col + e < N) dst[e] = v[e];
+        }
+      }
+  }
+}
+
+template <int BM, int BN, int SPLIT>
+constexpr int bf16_lds_elems() {
+  using T = Bf16Tile<BM, BN>;
+  return 2 * (SPLIT == 3 ? 2 : 1) * (T::A_PLANE + T::B_PLANE);
+}
+
+template <int BM, int BN, int SPLIT, int OCC>
+__global__ __launch_bounds__(kThreads, OCC) void coded_gemm_bf16_kernel(GemmParams p) {
+  __shared__ __attribute__((aligned(16))) us lds[bf16_lds_elems<BM, BN, SPLIT>()];
+  const int lin = xcd_remap(blockIdx.x, gridDim.x);
+  const int per_sym = p.tiles_m * p.tiles_n;
+  const int si = lin / per_sym;
+  const int rem = lin - si * per_sym;
+  const int mt = rem / p.tiles_n;
+  const int nt = rem - mt * p.tiles_n;
+  bf16_tile<BM, BN, SPLIT>(p, si, mt, nt, lds);
+}
+
+struct Bf16Entry {
+  TileShape shape;
+  void (*k1)(GemmParams);
+  void (*k3)(GemmParams);
+};
+
+const Bf16Entry kBf16Tiles[] = {
+    {{128, 128, 32}, coded_gemm_bf16_kernel<128, 128, 1, 2>, coded_gemm_bf16_kernel<128, 128, 3, 2>},
+    {{64, 128, 32}, coded_gemm_bf16_kernel<64, 128, 1, 2>, coded_gemm_bf16_kernel<64, 128, 3, 2>},
+    {{128, 256, 32}, coded_gemm_bf16_kernel<128, 256, 1, 1>, coded_gemm_bf16_kernel<128, 256, 3, 1>},
+    {{64, 256, 32}, coded_gemm_bf16_kernel<64, 256, 1, 1>, coded_gemm_bf16_kernel<64, 256, 3, 1>},
+};
+
+}  // namespace
+
+int32_t bf16_tile_count() { return (int32_t)(sizeof(kBf16Tiles) / sizeof(kBf16Tiles[0])); }
+TileShape bf16_tile_shape(int32_t t) { return kBf16Tiles[t].shape; }
+
+hipError_t launch_split_b(const float* B, int64_t ldb, int64_t K, int64_t N, int64_t Kp,
+                          void* bt_hi, void* bt_lo, hipStream_t stream) {
+  const dim3 grid((unsigned)((N + 63) / 64), (unsigned)((Kp + 63) / 64));
+  hipLaunchKernelGGL(split_b_kernel, grid, dim3(256), 0, stream, B, ldb, K, N, Kp,
+                     static_cast<us*>(bt_hi), static_cast<us*>(bt_lo));
+  return hipGetLastError();
+}
+
+hipError_t launch_coded_gemm_bf16(const GemmParams& p0, int32_t tile, hipStream_t stream) {
+  GemmParams p = p0;
+  const Bf16Entry& e = kBf16Tiles[tile];
+  p.tiles_m = (int32_t)((p.Mb + e.shape.bm - 1) / e.shape.bm);
+  p.tiles_n = (int32_t)((p.N + e.shape.bn - 1) / e.shape.bn);
+  const int64_t blocks = (int64_t)p.n_sym * p.tiles_m * p.tiles_n;
+  if (blocks == 0) return hipSuccess;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(p.prec == BPX_PREC_BF16X3 ? e.k3 : e.k1, dim3((unsigned)blocks),
+                     dim3(kThreads), 0, stream, p);
+  return hipGetLastError();
+}
+
+}  // namespace bpx

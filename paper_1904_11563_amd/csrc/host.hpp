@@ -69,6 +69,17 @@ struct bpx_plan {
   const int32_t* d_step_subs = nullptr;
 
   size_t y_bytes() const { return (size_t)n_yslots * (size_t)Mb * (size_t)N * sizeof(float); }
+  // K rounded up to the BF16 kernels' 32-wide k step
+  int64_t kp() const { return (K + 31) / 32 * 32; }
+  static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+  // Workspace: [Y slots][Bt_hi][Bt_lo] for the BF16 precisions.
+  size_t bt_plane_bytes() const { return align256((size_t)N * (size_t)kp() * 2); }
+  size_t ws_bytes() const {
+    size_t b = align256(y_bytes());
+    if (prec == BPX_PREC_BF16) b += bt_plane_bytes();
+    if (prec == BPX_PREC_BF16X3) b += 2 * bt_plane_bytes();
+    return b;
+  }
 };
 
 namespace bpx {

@@ -28,6 +28,10 @@ struct GemmParams {
   int32_t n_sym;
   int32_t tiles_m, tiles_n;
   int32_t prec;  // bpx_prec
+  // BF16 / BF16x3: B split into transposed bf16 planes (N x kp, k contiguous)
+  const unsigned short* bt_hi;
+  const unsigned short* bt_lo;
+  int64_t kp;
 };
 
 // Peel: see PeelStep in host.hpp.
@@ -61,6 +65,14 @@ int32_t gemm_tile_count();
 TileShape gemm_tile_shape(int32_t t);
 
 hipError_t launch_coded_gemm(const GemmParams& p, int32_t tile, hipStream_t stream);
+
+int32_t bf16_tile_count();
+TileShape bf16_tile_shape(int32_t t);
+// Bt_hi[n][k] = bf16(B[k][n]), Bt_lo = bf16(B - Bt_hi) (bt_lo may be null),
+// zero for k in [K, Kp).
+hipError_t launch_split_b(const float* B, int64_t ldb, int64_t K, int64_t N, int64_t Kp,
+                          void* bt_hi, void* bt_lo, hipStream_t stream);
+hipError_t launch_coded_gemm_bf16(const GemmParams& p, int32_t tile, hipStream_t stream);
 hipError_t launch_peel(const PeelParams& p, hipStream_t stream);
 hipError_t launch_encode(const EncodeParams& p, hipStream_t stream);
 

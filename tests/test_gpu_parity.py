@@ -294,3 +294,61 @@ def test_fp32_scale_full_size_sampled():
     _say("fp32_scale sampled relF", e)
     assert e <= TOL_F32
     assert np.isfinite(C).all()
+
+
+# ------------------------------------------------------------ BF16 paths --
+
+TOL_BF16X3 = 1e-5
+
+
+@pytest.mark.parametrize("prec", [bpx.PREC_BF16, bpx.PREC_BF16X3])
+def test_bf16_integer_operands_exact(prec):
+    # integers in [-8, 8] and their coded sums are exact in bf16 (lo = 0),
+    # products and FP32 accumulation are exact: the decode is bit exact.
+    code = code642()
+    M, K, N = 517, 260, 300
+    A = inputs.integers(11, inputs.TAG_A, (M, K))
+    B = inputs.integers(11, inputs.TAG_B, (K, N))
+    R = A.astype(np.float64) @ B.astype(np.float64)
+    for lost in [(0, 1), (2, 5), (3, 4)]:
+        order = [j for j in range(6) if j not in lost] + list(lost)
+        plan = bpx.Plan(code, order, 2, bpx.MODE_ERASURE, M, K, N, prec)
+        if not plan.decodable:
+            continue
+        C = run(plan, A, B)
+        assert np.array_equal(C.astype(np.float64), R), (prec, lost)
+
+
+def test_bf16x3_row_scaled_workload():
+    """512^3, A rows scaled log-uniformly in [1e-3, 1e3], (6,4,2) code with two
+    erased columns: split-BF16x3 must stay within 1e-5 of float64."""
+    w = inputs.WORKLOADS["bf16_small"]
+    A, B = inputs.operands(w, seed=0)
+    arrival, lost, _ = inputs.arrival_of(w, seed=0)
+    code = code642()
+    R = pipeline.uncoded(A, B)
+    errs = {}
+    for prec in (bpx.PREC_BF16X3, bpx.PREC_BF16):
+        plan = bpx.Plan(code, arrival, lost, bpx.MODE_ERASURE, w.M, w.K, w.N, prec)
+        C = run(plan, A, B)
+        errs[prec] = relf(C, R)
+    _say("bf16_small relF", errs)
+    assert errs[bpx.PREC_BF16X3] <= TOL_BF16X3
+    assert errs[bpx.PREC_BF16] <= 1e-2          # one bf16 rounding per operand
+
+
+def test_bf16x3_deep_chain_float():
+    """Table III's depth-9 chain: each release subtracts a decoded block, so
+    the independent errors of the degree-2 coded products add in quadrature
+    along the chain; block s at depth d carries about sqrt(2 d) times the
+    error e of one split-BF16x3 product (e <= 1e-5 is the single-product
+    bound).  Averaged over depths 1..9 that is sqrt(10) e."""
+    code = bpx.Code.table3()
+    M, K, N = 9 * 40, 256, 136
+    plan = bpx.Plan(code, [0, 1, 2, 3, 4], 2, bpx.MODE_ERASURE, M, K, N, bpx.PREC_BF16X3)
+    A = inputs.normal(12, inputs.TAG_A, (M, K))
+    B = inputs.normal(12, inputs.TAG_B, (K, N))
+    C = run(plan, A, B)
+    e = relf(C, pipeline.uncoded(A, B))
+    _say("bf16x3 depth-9 chain relF", e)
+    assert e <= TOL_BF16X3 * np.sqrt(10)

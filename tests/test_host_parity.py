@@ -192,5 +192,9 @@ def test_workspace_bytes():
     ws, enc = plan.workspace_bytes()
     dest = plan.schedule()["dest"]
     Mb = 10
-    assert ws == int((dest >= 0).sum()) * Mb * 10 * 4
+    al = lambda x: -(-x // 256) * 256
+    assert ws == al(int((dest >= 0).sum()) * Mb * 10 * 4)
     assert enc == len(dest) * Mb * 16 * 4
+    # BF16x3 adds two transposed bf16 planes of B (N x K rounded up to 32)
+    p3 = bpx.Plan(c, [3, 4, 0, 1, 2], 0, bpx.MODE_FULL, 90, 16, 10, bpx.PREC_BF16X3)
+    assert p3.workspace_bytes()[0] == ws + 2 * al(10 * 32 * 2)
