@@ -183,6 +183,23 @@ bpx_status bpx_plan_schedule(const bpx_plan* plan, const int32_t** computed,
 bpx_status bpx_plan_workspace_bytes(const bpx_plan* plan, size_t* ws_bytes,
                                     size_t* encode_bytes);
 
+/* Byte offsets of the parts of the plan's workspace (n entries written,
+ * at most 7), every part 256-byte aligned; a part the precision does not
+ * use has size 0 (its offset equals the next one); entry 6 is the total.
+ *   F32:     [0] Y slots
+ *   BF16*:   [0] Y, [1] Bt_hi, [2] Bt_lo: B rounded to bf16 (RNE) and the
+ *            bf16 residual, transposed (N x Kp, k contiguous, Kp = K rounded
+ *            up to 32, zero past K)
+ *   FP8*:    [0] Y, [1] Aq, [2] Aq2, [3] sA, [4] Bq, [5] sB: e4m3 codes of
+ *            the coded blocks ([n_computed][Mbp][Kp] bytes), of the FP8x2
+ *            residual term, their FP32 scales ([n_computed][Mbp/128][Kp/128]),
+ *            the codes of B transposed ([Np][Kp]) and its scales
+ *            ([Kp/128][Np/128]); Mbp, Kp, Np = Mb, K, N rounded up to 128.
+ * Per 128 x 128 block: s = amax / 448 (1 if amax = 0), code =
+ * e4m3(clamp(x / s, +-448)) with round to nearest even; the FP8x2 residual
+ * code is e4m3(clamp((x / s - code) * 16, +-448)). */
+bpx_status bpx_plan_workspace_layout(const bpx_plan* plan, size_t* offsets, int32_t n);
+
 /* Upload the plan's device tables now (hipMalloc + synchronous copy on the
  * current device).  Device calls do this on first use otherwise. */
 bpx_status bpx_plan_upload(bpx_plan* plan);
@@ -198,8 +215,11 @@ void bpx_plan_free(bpx_plan* plan);
 bpx_status bpx_encode(bpx_plan* plan, const float* A, int64_t lda, float* coded_out,
                       bpx_stream stream);
 
-/* Coded products: Y_g = C_g . B for every computed symbol, the encode fused
- * into the A-operand load (the coded block is never stored).  Products go to
+/* Coded products: Y_g = C_g . B for every computed symbol.  F32 and BF16*:
+ * the encode is fused into the A-operand load (the coded block is never
+ * stored).  FP8*: a streaming encode+quantise pass writes the e4m3 codes of
+ * every 128 x 128 coded tile (its scale needs the tile's amax), B is
+ * quantised once per call, then the block-scaled FP8 product runs.  Products go to
  * the Y slots of ws or, for degree-1 releasers, straight into C (see dest in
  * bpx_plan_schedule).  Precision is the plan's.  ws must hold ws_bytes. */
 bpx_status bpx_coded_gemm(bpx_plan* plan, const float* A, int64_t lda, const float* B,

@@ -37,6 +37,7 @@ MODE_NAMES = {"erasure": MODE_ERASURE, "straggler": MODE_STRAGGLER,
 EXPORTS = [
     "bpx_code_build", "bpx_code_from_csr", "bpx_code_info", "bpx_code_csr", "bpx_code_free",
     "bpx_plan_create", "bpx_plan_info", "bpx_plan_schedule", "bpx_plan_workspace_bytes",
+    "bpx_plan_workspace_layout",
     "bpx_plan_upload", "bpx_plan_free", "bpx_encode", "bpx_coded_gemm", "bpx_peel_decode",
     "bpx_coded_matmul", "bpx_coded_matmul_grouped", "bpx_grouped_extra_bytes",
     "bpx_tile_count", "bpx_set_tile_table", "bpx_force_tile", "bpx_last_error",
@@ -66,6 +67,7 @@ _sig = {
     "bpx_plan_schedule": (C.c_int, [_p] + [C.POINTER(_i32p)] * 5 + [C.POINTER(_u16p),
                                                                     C.POINTER(_i32p)]),
     "bpx_plan_workspace_bytes": (C.c_int, [_p, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+    "bpx_plan_workspace_layout": (C.c_int, [_p, C.POINTER(C.c_size_t), C.c_int32]),
     "bpx_plan_upload": (C.c_int, [_p]),
     "bpx_plan_free": (None, [_p]),
     "bpx_encode": (C.c_int, [_p, _p, C.c_int64, _p, _p]),
@@ -249,6 +251,12 @@ class Plan:
         ws, enc = C.c_size_t(), C.c_size_t()
         _check(_lib.bpx_plan_workspace_bytes(self._h, C.byref(ws), C.byref(enc)))
         return ws.value, enc.value
+
+    def workspace_layout(self):
+        """Byte offsets of the workspace parts (see bpx_plan_workspace_layout)."""
+        off = (C.c_size_t * 7)()
+        _check(_lib.bpx_plan_workspace_layout(self._h, off, 7))
+        return list(off)
 
     def upload(self):
         _check(_lib.bpx_plan_upload(self._h))

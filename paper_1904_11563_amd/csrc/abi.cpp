@@ -108,8 +108,7 @@ bpx_status check_device_call(bpx_plan* plan) {
   if (!plan) return fail(BPX_E_INVALID, "null plan");
   if (!plan->decodable) return fail(BPX_E_UNDECODABLE, "plan is not decodable");
   if (plan->K % 4 != 0) return fail(BPX_E_INVALID, "K must be a multiple of 4");
-  if (plan->prec != BPX_PREC_F32 && plan->prec != BPX_PREC_BF16 &&
-      plan->prec != BPX_PREC_BF16X3)
+  if (plan->prec < BPX_PREC_F32 || plan->prec > BPX_PREC_FP8X2)
     return fail(BPX_E_UNSUPPORTED, "precision not built into this library");
   return upload(plan);
 }
@@ -153,7 +152,39 @@ bpx_status gemm_impl(bpx_plan* plan, const float* A, int64_t lda, const float* B
     return fail(BPX_E_UNSUPPORTED, "block too large for 32-bit tile offsets");
   const int32_t tile = choose_tile(plan->prec, plan->Mb, plan->N, plan->K);
   hipError_t e;
-  if (plan->prec == BPX_PREC_BF16 || plan->prec == BPX_PREC_BF16X3) {
+  if (plan->is_fp8()) {
+    size_t off[7];
+    plan->layout(off);
+    char* w = static_cast<char*>(ws);
+    Fp8Params f{};
+    f.A = A;
+    f.lda = lda;
+    f.B = B;
+    f.ldb = ldb;
+    f.C = C;
+    f.ldc = ldc;
+    f.Y = static_cast<float*>(ws);
+    f.M = plan->M;
+    f.K = plan->K;
+    f.N = plan->N;
+    f.Mb = plan->Mb;
+    f.Mbp = plan->r128(plan->Mb);
+    f.Kp = plan->r128(plan->K);
+    f.Np = plan->r128(plan->N);
+    f.syms = plan->d_gemm_syms;
+    f.ids = plan->d_gemm_ids;
+    f.n_sym = (int32_t)plan->computed.size();
+    f.aq = reinterpret_cast<unsigned char*>(w + off[1]);
+    f.aq2 = plan->prec == BPX_PREC_FP8X2 ? reinterpret_cast<unsigned char*>(w + off[2]) : nullptr;
+    f.sa = reinterpret_cast<float*>(w + off[3]);
+    f.bq = reinterpret_cast<unsigned char*>(w + off[4]);
+    f.sb = reinterpret_cast<float*>(w + off[5]);
+    if (f.Np / 128 > 65535 || f.Kp / 128 > 65535 || f.Mbp / 128 > 65535 || f.n_sym > 65535)
+      return fail(BPX_E_UNSUPPORTED, "FP8 grid too large");
+    e = launch_quant_b(f, stream);
+    if (e == hipSuccess) e = launch_quant_a(f, stream);
+    if (e == hipSuccess) e = launch_coded_gemm_fp8(f, stream);
+  } else if (plan->prec == BPX_PREC_BF16 || plan->prec == BPX_PREC_BF16X3) {
     char* planes = static_cast<char*>(ws) + bpx_plan::align256(plan->y_bytes());
     void* hi = planes;
     void* lo = plan->prec == BPX_PREC_BF16X3 ? planes + plan->bt_plane_bytes() : nullptr;
@@ -325,6 +356,14 @@ bpx_status bpx_plan_workspace_bytes(const bpx_plan* plan, size_t* ws_bytes,
   if (ws_bytes) *ws_bytes = plan->ws_bytes();
   if (encode_bytes)
     *encode_bytes = plan->computed.size() * (size_t)plan->Mb * (size_t)plan->K * sizeof(float);
+  return BPX_OK;
+}
+
+bpx_status bpx_plan_workspace_layout(const bpx_plan* plan, size_t* offsets, int32_t n) {
+  if (!plan || !offsets || n < 1) return fail(BPX_E_INVALID, "null argument");
+  size_t off[7];
+  plan->layout(off);
+  for (int32_t i = 0; i < n && i < 7; ++i) offsets[i] = off[i];
   return BPX_OK;
 }
 

@@ -1,0 +1,330 @@
+// FP8-e4m3 coded products with one FP32 scale per 128 x 128 block.
+//
+// quant_a_kernel  - the encode for FP8: per computed symbol g and 128 x 128
+//                   tile of its coded block C_g = sum of its data blocks A_s
+//                   (Sec. II, XOR read as a real sum), sum the members in
+//                   FP32 (ascending), take the tile's amax, scale
+//                   s = amax / 448 (s = 1 when amax = 0) and store
+//                   q = e4m3(clamp(x / s, +-448)) (round to nearest even).
+//                   FP8x2 also stores the residual term
+//                   q2 = e4m3(clamp((x / s - q) * 16, +-448)), so that
+//                   x ~ s (q + q2 / 16).
+// quant_b_kernel  - the same for B, written transposed (N x Kp, k
+//                   contiguous) so that both MFMA operands read k runs.
+// coded_gemm_fp8  - Y_g = sum over 128-wide k chunks of sA sB (qA . qB), the
+//                   chunk product on v_mfma_scale_f32_16x16x128_f8f6f4 with
+//                   unit E8M0 scales, the FP32 scaling applied per chunk.
+//
+// The encode cannot be folded into the GEMM prologue here: a tile's scale
+// needs the amax of the whole 128 x 128 coded tile, and every N-tile of the
+// GEMM would repeat the FP32 reads and the reduction; one streaming pass
+// that writes 1-byte codes is cheaper.
+//
+// Workspace layout (bytes, each part 256-aligned, see bpx_plan::fp8_layout):
+//   Y slots | Aq [n_sym][Mbp][Kp] | Aq2 (FP8x2) | sA [n_sym][Mbp/128][Kp/128]
+//   | Bq [Np][Kp] | sB [Kp/128][Np/128]
+// with Mbp = Mb rounded up to 128, Kp = K rounded up to 128, Np = N rounded
+// up to 128; padding rows/columns are zero codes.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace bpx {
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+
+constexpr float kE4M3Max = 448.f;
+
+__device__ __forceinline__ float clamp448(float v) {
+  return v > kE4M3Max ? kE4M3Max : (v < -kE4M3Max ? -kE4M3Max : v);
+}
+
+// Four e4m3 codes of four floats, packed little-endian into one int.
+__device__ __forceinline__ int pack_e4m3(v4f v) {
+  int w = __builtin_amdgcn_cvt_pk_fp8_f32(clamp448(v[0]), clamp448(v[1]), 0, false);
+  return __builtin_amdgcn_cvt_pk_fp8_f32(clamp448(v[2]), clamp448(v[3]), w, true);
+}
+__device__ __forceinline__ v4f unpack_e4m3(int w) {
+  return v4f{__builtin_amdgcn_cvt_f32_fp8(w, 0), __builtin_amdgcn_cvt_f32_fp8(w, 1),
+             __builtin_amdgcn_cvt_f32_fp8(w, 2), __builtin_amdgcn_cvt_f32_fp8(w, 3)};
+}
+
+__device__ __forceinline__ float block_amax(float m, float* red) {
+  // wave reduction then across the 4 waves of the block
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = m;
+  __syncthreads();
+  m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  __syncthreads();
+  return m;
+}
+
+// grid: (Kp/128, Mbp/128, n_sym), 256 threads; thread t owns float4 chunks
+// f = t + 256 i (i < 16): row f / 32, k offset (f % 32) * 4 of the tile.
+__global__ __launch_bounds__(256) void quant_a_kernel(Fp8Params p) {
+  __shared__ float red[4];
+  const int kb = blockIdx.x, rb = blockIdx.y, si = blockIdx.z;
+  const int id_off = p.syms[4 * si + 0];
+  const int deg = p.syms[4 * si + 1];
+  const int32_t* ids = p.ids + id_off;
+  const int64_t k0 = (int64_t)kb * 128, r0 = (int64_t)rb * 128;
+  v4f x[16];
+  float amax = 0.f;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int f = threadIdx.x + 256 * i;
+    const int64_t r = r0 + f / 32, k = k0 + (f % 32) * 4;
+    v4f s = {0.f, 0.f, 0.f, 0.f};
+    if (r < p.Mb && k < p.K) {
+      for (int m = 0; m < deg; ++m) {
+        const int64_t row = (int64_t)ids[m] * p.Mb + r;
+        if (row < p.M) s += *reinterpret_cast<const v4f*>(p.A + row * p.lda + k);
+      }
+    }
+    x[i] = s;
+    amax = fmaxf(amax, fmaxf(fmaxf(fabsf(s[0]), fabsf(s[1])), fmaxf(fabsf(s[2]), fabsf(s[3]))));
+  }
+  amax = block_amax(amax, red);
+  const float sc = amax > 0.f ? amax / kE4M3Max : 1.f;
+  const int64_t sym_bytes = p.Mbp * p.Kp;
+  unsigned char* q = p.aq + (int64_t)si * sym_bytes;
+  unsigned char* q2 = p.aq2 ? p.aq2 + (int64_t)si * sym_bytes : nullptr;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int f = threadIdx.x + 256 * i;
+    const int64_t r = r0 + f / 32, k = k0 + (f % 32) * 4;
+    const v4f v = x[i] / sc;
+    const int w = pack_e4m3(v);
+    *reinterpret_cast<int*>(q + r * p.Kp + k) = w;
+    if (q2) *reinterpret_cast<int*>(q2 + r * p.Kp + k) = pack_e4m3((v - unpack_e4m3(w)) * 16.f);
+  }
+  if (threadIdx.x == 0) p.sa[((int64_t)si * (p.Mbp / 128) + rb) * (p.Kp / 128) + kb] = sc;
+}
+
+// grid: (Np/128, Kp/128), 256 threads.  Reads a 128 (k) x 128 (n) block of B
+// coalesced along n, writes codes transposed through LDS.
+__global__ __launch_bounds__(256) void quant_b_kernel(Fp8Params p) {
+  __shared__ float red[4];
+  __shared__ unsigned char t[128][132];
+  const int nb = blockIdx.x, kb = blockIdx.y;
+  const int64_t n0 = (int64_t)nb * 128, k0 = (int64_t)kb * 128;
+  v4f x[16];
+  float amax = 0.f;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int f = threadIdx.x + 256 * i;
+    const int64_t k = k0 + f / 32, n = n0 + (f % 32) * 4;
+    v4f s = {0.f, 0.f, 0.f, 0.f};
+    if (k < p.K) {
+      const float* src = p.B + k * p.ldb + n;
+      if (n + 3 < p.N) {
+        s = *reinterpret_cast<const v4f*>(src);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (n + e < p.N) s[e] = src[e];
+      }
+    }
+    x[i] = s;
+    amax = fmaxf(amax, fmaxf(fmaxf(fabsf(s[0]), fabsf(s[1])), fmaxf(fabsf(s[2]), fabsf(s[3]))));
+  }
+  amax = block_amax(amax, red);
+  const float sc = amax > 0.f ? amax / kE4M3Max : 1.f;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int f = threadIdx.x + 256 * i;
+    const int kl = f / 32, nl = (f % 32) * 4;
+    const int w = pack_e4m3(x[i] / sc);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) t[nl + e][kl] = (unsigned char)((w >> (8 * e)) & 0xff);
+  }
+  __syncthreads();
+  // 128 rows (n) of 128 code bytes: thread writes 16-byte pieces
+  for (int f = threadIdx.x; f < 128 * 8; f += 256) {
+    const int nl = f / 8, kc = (f % 8) * 16;
+    uint4 v;
+    v.x = *reinterpret_cast<const unsigned*>(&t[nl][kc + 0]);
+    v.y = *reinterpret_cast<const unsigned*>(&t[nl][kc + 4]);
+    v.z = *reinterpret_cast<const unsigned*>(&t[nl][kc + 8]);
+    v.w = *reinterpret_cast<const unsigned*>(&t[nl][kc + 12]);
+    *reinterpret_cast<uint4*>(p.bq + (n0 + nl) * p.Kp + k0 + kc) = v;
+  }
+  if (threadIdx.x == 0) p.sb[(int64_t)kb * (p.Np / 128) + nb] = sc;
+}
+
+// ----------------------------------------------------------------- GEMM --
+constexpr int kThreads = 256;
+constexpr int CK = 128;       // k chunk = scale block
+constexpr int RS = CK + 16;   // LDS row stride in bytes
+
+__device__ __forceinline__ int xcd_remap(int lin, int total) {
+  if ((total & 7) != 0) return lin;
+  return (lin & 7) * (total >> 3) + (lin >> 3);
+}
+
+template <int X2>
+__global__ __launch_bounds__(kThreads, 1) void coded_gemm_fp8_kernel(Fp8Params p) {
+  constexpr int BM = 128, BN = 128, TM = 64, TN = 64, FM = 4, FN = 4;
+  constexpr int NA = X2 ? 2 : 1;                  // A planes
+  constexpr int STAGE = (NA * BM + BN) * RS;       // bytes per stage
+  __shared__ __attribute__((aligned(16))) unsigned char lds[2 * STAGE];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int q = lane >> 4, c16 = lane & 15;
+
+  const int lin = xcd_remap(blockIdx.x, gridDim.x);
+  const int per_sym = p.tiles_m * p.tiles_n;
+  const int si = lin / per_sym;
+  const int rem = lin - si * per_sym;
+  const int mt = rem / p.tiles_n;
+  const int nt = rem - mt * p.tiles_n;
+  const int m0 = mt * BM, n0 = nt * BN;
+  const int dest = p.syms[4 * si + 2];
+
+  const int64_t sym_bytes = p.Mbp * p.Kp;
+  const unsigned char* Aq = p.aq + (int64_t)si * sym_bytes + (int64_t)m0 * p.Kp;
+  const unsigned char* Aq2 = X2 ? p.aq2 + (int64_t)si * sym_bytes + (int64_t)m0 * p.Kp : nullptr;
+  const unsigned char* Bq = p.bq + (int64_t)n0 * p.Kp;
+  const float* sa = p.sa + ((int64_t)si * (p.Mbp / 128) + mt) * (p.Kp / 128);
+  const float* sb = p.sb + nt;
+  const int64_t np128 = p.Np / 128;
+
+  // 16-byte pieces: row f / 8, byte offset (f % 8) * 16; 4 per thread per plane
+  uint4 ra[NA][4], rbv[4];
+  auto load = [&](int c) __attribute__((always_inline)) {
+    const int64_t kc = (int64_t)c * CK;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int f = tid + kThreads * i;
+      const int64_t off = (int64_t)(f / 8) * p.Kp + kc + (f % 8) * 16;
+      ra[0][i] = *reinterpret_cast<const uint4*>(Aq + off);
+      if (X2) ra[NA - 1][i] = *reinterpret_cast<const uint4*>(Aq2 + off);
+      rbv[i] = *reinterpret_cast<const uint4*>(Bq + off);
+    }
+  };
+  auto store = [&](int buf) __attribute__((always_inline)) {
+    unsigned char* st = lds + buf * STAGE;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int f = tid + kThreads * i;
+      const int o = (f / 8) * RS + (f % 8) * 16;
+#pragma unroll
+      for (int a = 0; a < NA; ++a) *reinterpret_cast<uint4*>(st + a * BM * RS + o) = ra[a][i];
+      *reinterpret_cast<uint4*>(st + NA * BM * RS + o) = rbv[i];
+    }
+  };
+
+  v4f acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  const int nc = (int)(p.Kp / CK);
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int c = 0; c < nc; ++c) {
+    const bool more = c + 1 < nc;
+    if (more) load(c + 1);
+    const unsigned char* st = lds + (c & 1) * STAGE;
+    v8i a[NA][FM], b[FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int pl = 0; pl < NA; ++pl)
+        a[pl][i] = *reinterpret_cast<const v8i*>(st + pl * BM * RS +
+                                                 (wm * TM + i * 16 + c16) * RS + 32 * q);
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int n = wn * TN + 4 * c16 + j;   // interleaved output columns
+      b[j] = *reinterpret_cast<const v8i*>(st + NA * BM * RS + n * RS + 32 * q);
+    }
+    const float s = sa[c] * sb[(int64_t)c * np128];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        v4f part = {0.f, 0.f, 0.f, 0.f};
+        if (X2) {
+          part = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[1][i], b[j], part, 0, 0, 0,
+                                                                   127, 0, 127);
+          part *= 0.0625f;  // the residual term carries a factor 16
+        }
+        part = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[0][i], b[j], part, 0, 0, 0,
+                                                                 127, 0, 127);
+        acc[i][j] += s * part;
+      }
+    if (more) store((c + 1) & 1);
+    __syncthreads();
+  }
+
+  float* out;
+  int64_t ldo, rows;
+  const int64_t Mb = p.Mb, N = p.N, M = p.M;
+  if (dest >= 0) {
+    out = p.Y + (int64_t)dest * Mb * N;
+    ldo = N;
+    rows = Mb;
+  } else {
+    const int64_t sb_ = -1 - dest;
+    out = p.C + sb_ * Mb * p.ldc;
+    ldo = p.ldc;
+    rows = M - sb_ * Mb < Mb ? M - sb_ * Mb : Mb;
+  }
+  const bool vec_ok = (ldo & 3) == 0;
+  const int64_t col = n0 + wn * TN + 4 * c16;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = m0 + wm * TM + i * 16 + 4 * q + r;
+      if (row >= rows) continue;
+      float* dst = out + row * ldo + col;
+      const v4f v = {acc[i][0][r], acc[i][1][r], acc[i][2][r], acc[i][3][r]};
+      if (col + 3 < N && vec_ok) {
+        *reinterpret_cast<v4f*>(dst) = v;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (col + e < N) dst[e] = v[e];
+      }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_quant_a(const Fp8Params& p, hipStream_t stream) {
+  if (p.n_sym == 0) return hipSuccess;
+  const dim3 grid((unsigned)(p.Kp / 128), (unsigned)(p.Mbp / 128), (unsigned)p.n_sym);
+  hipLaunchKernelGGL(quant_a_kernel, grid, dim3(256), 0, stream, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_quant_b(const Fp8Params& p, hipStream_t stream) {
+  const dim3 grid((unsigned)(p.Np / 128), (unsigned)(p.Kp / 128));
+  hipLaunchKernelGGL(quant_b_kernel, grid, dim3(256), 0, stream, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_coded_gemm_fp8(const Fp8Params& p0, hipStream_t stream) {
+  Fp8Params p = p0;
+  p.tiles_m = (int32_t)((p.Mb + 127) / 128);
+  p.tiles_n = (int32_t)((p.N + 127) / 128);
+  const int64_t blocks = (int64_t)p.n_sym * p.tiles_m * p.tiles_n;
+  if (blocks == 0) return hipSuccess;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  if (p.aq2)
+    hipLaunchKernelGGL(coded_gemm_fp8_kernel<1>, dim3((unsigned)blocks), dim3(kThreads), 0,
+                       stream, p);
+  else
+    hipLaunchKernelGGL(coded_gemm_fp8_kernel<0>, dim3((unsigned)blocks), dim3(kThreads), 0,
+                       stream, p);
+  return hipGetLastError();
+}
+
+}  // namespace bpx

@@ -74,11 +74,47 @@ struct bpx_plan {
   static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
   // Workspace: [Y slots][Bt_hi][Bt_lo] for the BF16 precisions.
   size_t bt_plane_bytes() const { return align256((size_t)N * (size_t)kp() * 2); }
-  size_t ws_bytes() const {
+  // FP8: [Y][Aq][Aq2][sA][Bq][sB] with Mb, K, N rounded up to 128.
+  int64_t r128(int64_t x) const { return (x + 127) / 128 * 128; }
+  bool is_fp8() const { return prec == BPX_PREC_FP8 || prec == BPX_PREC_FP8X2; }
+  bool is_bf16() const { return prec == BPX_PREC_BF16 || prec == BPX_PREC_BF16X3; }
+  // Offsets in bytes of the workspace parts:
+  //   F32:    [0] Y
+  //   BF16*:  [0] Y, [1] Bt_hi, [2] Bt_lo (BF16x3)
+  //   FP8*:   [0] Y, [1] Aq, [2] Aq2 (FP8x2), [3] sA, [4] Bq, [5] sB
+  // Missing parts get the offset of the next part (size 0).  [6] = total.
+  void layout(size_t off[7]) const {
     size_t b = align256(y_bytes());
-    if (prec == BPX_PREC_BF16) b += bt_plane_bytes();
-    if (prec == BPX_PREC_BF16X3) b += 2 * bt_plane_bytes();
-    return b;
+    for (int i = 0; i < 7; ++i) off[i] = 0;
+    if (is_bf16()) {
+      off[1] = b;
+      b += bt_plane_bytes();
+      off[2] = b;
+      if (prec == BPX_PREC_BF16X3) b += bt_plane_bytes();
+      for (int i = 3; i < 7; ++i) off[i] = b;
+    } else if (is_fp8()) {
+      const size_t nc = computed.size();
+      const size_t aq = align256(nc * (size_t)r128(Mb) * (size_t)r128(K));
+      off[1] = b;
+      b += aq;
+      off[2] = b;
+      if (prec == BPX_PREC_FP8X2) b += aq;
+      off[3] = b;
+      b += align256(nc * (size_t)(r128(Mb) / 128) * (size_t)(r128(K) / 128) * 4);
+      off[4] = b;
+      b += align256((size_t)r128(N) * (size_t)r128(K));
+      off[5] = b;
+      b += align256((size_t)(r128(K) / 128) * (size_t)(r128(N) / 128) * 4);
+      off[6] = b;
+    } else {
+      for (int i = 1; i < 7; ++i) off[i] = b;
+    }
+    off[6] = b;
+  }
+  size_t ws_bytes() const {
+    size_t off[7];
+    layout(off);
+    return off[6];
   }
 };
 

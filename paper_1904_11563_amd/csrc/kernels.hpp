@@ -34,6 +34,28 @@ struct GemmParams {
   int64_t kp;
 };
 
+// FP8 path (see gemm_fp8.hip for the workspace layout).
+struct Fp8Params {
+  const float* A;
+  int64_t lda;
+  const float* B;
+  int64_t ldb;
+  float* C;
+  int64_t ldc;
+  float* Y;
+  int64_t M, K, N, Mb;
+  int64_t Mbp, Kp, Np;  // Mb, K, N rounded up to 128
+  const int32_t* syms;
+  const int32_t* ids;
+  int32_t n_sym;
+  int32_t tiles_m, tiles_n;
+  unsigned char* aq;
+  unsigned char* aq2;  // null unless FP8x2
+  float* sa;
+  unsigned char* bq;
+  float* sb;
+};
+
 // Peel: see PeelStep in host.hpp.
 struct PeelParams {
   const float* Y;
@@ -73,6 +95,9 @@ TileShape bf16_tile_shape(int32_t t);
 hipError_t launch_split_b(const float* B, int64_t ldb, int64_t K, int64_t N, int64_t Kp,
                           void* bt_hi, void* bt_lo, hipStream_t stream);
 hipError_t launch_coded_gemm_bf16(const GemmParams& p, int32_t tile, hipStream_t stream);
+hipError_t launch_quant_a(const Fp8Params& p, hipStream_t stream);
+hipError_t launch_quant_b(const Fp8Params& p, hipStream_t stream);
+hipError_t launch_coded_gemm_fp8(const Fp8Params& p, hipStream_t stream);
 hipError_t launch_peel(const PeelParams& p, hipStream_t stream);
 hipError_t launch_encode(const EncodeParams& p, hipStream_t stream);
 

@@ -352,3 +352,96 @@ def test_bf16x3_deep_chain_float():
     e = relf(C, pipeline.uncoded(A, B))
     _say("bf16x3 depth-9 chain relF", e)
     assert e <= TOL_BF16X3 * np.sqrt(10)
+
+
+# ------------------------------------------------------------- FP8 paths --
+
+TOL_FP8 = 3e-2
+
+
+def test_fp8_codes_and_scales_match_oracle():
+    """The FP8 encode+quantise pass: every code byte and scale of the coded
+    A tiles (and the FP8x2 residual codes) and of B equals the oracle's
+    quantiser, which follows the OCP e4m3 definition in the same float32
+    order (ragged M, K, N)."""
+    from oracle import quant
+    code = code642()
+    oc = oracle_of(code)
+    M, K, N = 300, 260, 200
+    A = inputs.normal(21, inputs.TAG_A, (M, K))
+    B = inputs.normal(21, inputs.TAG_B, (K, N))
+    plan = bpx.Plan(code, [5, 3, 0, 1, 2, 4], 0, bpx.MODE_STRAGGLER, M, K, N, bpx.PREC_FP8X2)
+    Ad, Bd = padded(A), padded(B)
+    Cd = torch.zeros((M, -(-N // 4) * 4), device="cuda")[:, :N]
+    ws = bpx.alloc_workspace(plan)
+    bpx.coded_gemm(plan, Ad, Bd, Cd, ws)
+    raw = host(ws)
+    off = plan.workspace_layout()
+    Mb = plan.info()["Mb"]
+    r = lambda x: -(-x // 128) * 128
+    Mbp, Kp, Np = r(Mb), r(K), r(N)
+    comp = plan.schedule()["computed"].tolist()
+    aq = raw[off[1]:off[1] + len(comp) * Mbp * Kp].reshape(len(comp), Mbp, Kp)
+    aq2 = raw[off[2]:off[2] + len(comp) * Mbp * Kp].reshape(len(comp), Mbp, Kp)
+    sa = raw[off[3]:off[3] + len(comp) * (Mbp // 128) * (Kp // 128) * 4].view(np.float32)
+    sa = sa.reshape(len(comp), Mbp // 128, Kp // 128)
+    bq = raw[off[4]:off[4] + Np * Kp].reshape(Np, Kp)
+    sb = raw[off[5]:off[5] + (Kp // 128) * (Np // 128) * 4].view(np.float32).reshape(Kp // 128, Np // 128)
+    sym = {g: d for g, _, d in oc.symbols()}
+    for i, g in enumerate(comp):
+        blk = np.zeros((Mbp, Kp), dtype=np.float32)
+        blk[:Mb, :K] = quant.coded_block_fp32(A, Mb, sym[g], M)
+        for rb in range(Mbp // 128):
+            for kb in range(Kp // 128):
+                tile = blk[rb * 128:(rb + 1) * 128, kb * 128:(kb + 1) * 128]
+                s, c1, c2 = quant.quantize_block(tile, residual=True)
+                assert sa[i, rb, kb] == s, (g, rb, kb)
+                got1 = aq[i, rb * 128:(rb + 1) * 128, kb * 128:(kb + 1) * 128]
+                got2 = aq2[i, rb * 128:(rb + 1) * 128, kb * 128:(kb + 1) * 128]
+                assert np.array_equal(got1, c1), (g, rb, kb, np.argwhere(got1 != c1)[:3])
+                assert np.array_equal(got2, c2), (g, rb, kb)
+    Bp = np.zeros((Kp, Np), dtype=np.float32)
+    Bp[:K, :N] = B
+    for kb in range(Kp // 128):
+        for nb in range(Np // 128):
+            s, c = quant.quantize_block(Bp[kb * 128:(kb + 1) * 128, nb * 128:(nb + 1) * 128])
+            assert sb[kb, nb] == s
+            assert np.array_equal(bq[nb * 128:(nb + 1) * 128, kb * 128:(kb + 1) * 128], c.T)
+
+
+def test_fp8_mojette_end_to_end():
+    """Mojette Construction A (k=16, n=24, b=8), 8 of 24 columns erased, at a
+    reduced M, K, N: FP8x2 within 3e-2 of float64; 1-pass FP8 reported."""
+    code = bpx.Code.mojette(16, 8, 24, 0)
+    M, K, N = 4096, 1024, 640
+    A = inputs.normal(22, inputs.TAG_A, (M, K))
+    B = inputs.normal(22, inputs.TAG_B, (K, N))
+    R = pipeline.uncoded(A, B)
+    errs = {}
+    for seed in range(3):
+        arrival, lost = inputs.erasure_arrival(seed, 24, 8)
+        for prec in (bpx.PREC_FP8X2, bpx.PREC_FP8):
+            plan = bpx.Plan(code, arrival, lost, bpx.MODE_ERASURE, M, K, N, prec)
+            C = run(plan, A, B)
+            errs[(seed, prec, plan.info()["prefix_m"])] = relf(C, R)
+    _say("fp8 mojette relF", errs)
+    # 1-pass FP8 has no accuracy target: one e4m3 rounding per operand
+    # already gives ~3.7e-2 uncoded, and a release through a degree-d bin
+    # moves the quantisation error of the whole d-block sum onto one block.
+    # It gets a loose sanity bound; FP8x2 must meet the 3e-2 target.
+    for (seed, prec, m), e in errs.items():
+        assert e <= (TOL_FP8 if prec == bpx.PREC_FP8X2 else 0.1), (seed, prec, m, e)
+
+
+def test_fp8_integer_operands_small_chain():
+    # Table III depth-9 chain through the FP8x2 path: the relative error
+    # stays at the FP8 level (no blow-up through the subtraction chain).
+    code = bpx.Code.table3()
+    M, K, N = 9 * 64, 512, 256
+    A = inputs.normal(23, inputs.TAG_A, (M, K))
+    B = inputs.normal(23, inputs.TAG_B, (K, N))
+    plan = bpx.Plan(code, [0, 1, 2, 3, 4], 2, bpx.MODE_ERASURE, M, K, N, bpx.PREC_FP8X2)
+    C = run(plan, A, B)
+    e = relf(C, pipeline.uncoded(A, B))
+    _say("fp8x2 depth-9 chain relF", e)
+    assert e <= TOL_FP8 * np.sqrt(10)
