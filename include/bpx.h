@@ -238,29 +238,50 @@ bpx_status bpx_coded_matmul(bpx_plan* plan, const float* A, int64_t lda, const f
                             int64_t ldb, float* C, int64_t ldc, void* ws, size_t ws_bytes,
                             bpx_stream stream);
 
-/* Many independent coded products in one launch sequence.  plans[i] gives
- * product i's code, arrival pattern, shape and precision (all plans must
- * share one precision); A[i], B[i], C[i] are its operands with leading
- * dimensions equal to K, N, N.  ws must hold the sum over i of each plan's
- * ws_bytes rounded up to 256 bytes, plus bpx_grouped_extra_bytes(count).
- * Any undecodable plan makes the call return BPX_E_UNDECODABLE before any
- * launch. */
+/* ------------------------------------------------------------- groups -- */
+
+/* Many independent coded products, each with its own code, arrival pattern
+ * and shape, in one launch sequence that allocates nothing, so that it can
+ * be captured once in a HIP graph and replayed.  Operands of product i are
+ * dense row-major: A[i] (M x K, lda = K), B[i] (K x N, ldb = N), C[i]
+ * (M x N, ldc = N), K and N multiples of 4, 16-byte aligned.  All plans must
+ * share one precision, BF16 or BF16x3.
+ *
+ * bpx_group_workspace_bytes: device workspace for the plans (each plan's
+ *   bpx_plan_workspace_bytes rounded up to 256, back to back).
+ * bpx_group_create: host setup, done once: uploads the plans' tables and one
+ *   block of per-product descriptors and a tile list (hipMalloc + one
+ *   synchronous copy).  ws (256-byte aligned) and every operand pointer are
+ *   baked into the descriptors and must stay valid while the group lives.
+ *   Each product gets the GEMM tile shape bpx_set_tile_table selects for
+ *   its (Mb, N, K); tiles of one shape form one persistent launch whose
+ *   workgroups stride over the tile list, longest K first.
+ *   Returns BPX_E_UNDECODABLE if any plan is undecodable (nothing created).
+ * bpx_group_launch: enqueue, on stream: one grouped B-split launch, one
+ *   persistent grouped GEMM launch per tile shape present, one grouped peel
+ *   launch.  No allocation, copy or synchronisation: graph-capturable.
+ *   Calls on one group must not overlap (they share the workspace).
+ * bpx_coded_matmul_grouped: create, launch, synchronise the stream, free. */
+typedef struct bpx_group bpx_group;
+bpx_status bpx_group_workspace_bytes(bpx_plan* const* plans, int32_t count, size_t* bytes);
+bpx_status bpx_group_create(bpx_plan* const* plans, const float* const* A, const float* const* B,
+                            float* const* C, int32_t count, void* ws, size_t ws_bytes,
+                            bpx_group** out);
+bpx_status bpx_group_launch(bpx_group* group, bpx_stream stream);
+void bpx_group_free(bpx_group* group);
 bpx_status bpx_coded_matmul_grouped(bpx_plan* const* plans, const float* const* A,
                                     const float* const* B, float* const* C, int32_t count,
                                     void* ws, size_t ws_bytes, bpx_stream stream);
 
-/* Extra workspace bytes the grouped call needs for its descriptors. */
-size_t bpx_grouped_extra_bytes(int32_t count);
-
-/* Tile-shape selection: the grouped and single-product GEMM pick one of the
- * compiled tile shapes per product.  bpx_tile_count() returns the number of
- * shapes; bpx_set_tile_table installs an autotuned table mapping shape
- * buckets (log2 of M/128, N/128, K/128 clamped to [0, 7], and the precision)
- * to a tile-shape index; entries < 0 fall back to the default choice.  The
- * table has 8*8*8*5 entries indexed ((prec*8 + bm)*8 + bn)*8 + bk. */
-int32_t bpx_tile_count(void);
+/* Tile-shape selection.  bpx_tile_count(prec) returns the number of compiled
+ * GEMM tile shapes for a precision; bpx_set_tile_table installs an autotuned
+ * table mapping shape buckets (log2 of ceil(x/128), clamped to [0, 7], for
+ * x = Mb, N, K) and the precision to a tile-shape index, indexed
+ * ((prec*8 + bMb)*8 + bN)*8 + bK (8*8*8*5 entries; NULL clears it; entries
+ * < 0 fall back to the default shape).  bpx_force_tile forces one shape for
+ * every call (for the autotuner); -1 returns to the table. */
+int32_t bpx_tile_count(int32_t prec);
 bpx_status bpx_set_tile_table(const int32_t* table, int32_t n_entries);
-/* Force one tile shape for every call (for the autotuner); -1 = table. */
 bpx_status bpx_force_tile(int32_t tile);
 
 const char* bpx_last_error(void);

@@ -39,7 +39,8 @@ EXPORTS = [
     "bpx_plan_create", "bpx_plan_info", "bpx_plan_schedule", "bpx_plan_workspace_bytes",
     "bpx_plan_workspace_layout",
     "bpx_plan_upload", "bpx_plan_free", "bpx_encode", "bpx_coded_gemm", "bpx_peel_decode",
-    "bpx_coded_matmul", "bpx_coded_matmul_grouped", "bpx_grouped_extra_bytes",
+    "bpx_coded_matmul", "bpx_coded_matmul_grouped", "bpx_group_workspace_bytes",
+    "bpx_group_create", "bpx_group_launch", "bpx_group_free",
     "bpx_tile_count", "bpx_set_tile_table", "bpx_force_tile", "bpx_last_error",
 ]
 
@@ -78,8 +79,12 @@ _sig = {
                                    C.c_size_t, _p]),
     "bpx_coded_matmul_grouped": (C.c_int, [C.POINTER(_p), C.POINTER(_p), C.POINTER(_p),
                                            C.POINTER(_p), C.c_int32, _p, C.c_size_t, _p]),
-    "bpx_grouped_extra_bytes": (C.c_size_t, [C.c_int32]),
-    "bpx_tile_count": (C.c_int32, []),
+    "bpx_group_workspace_bytes": (C.c_int, [C.POINTER(_p), C.c_int32, C.POINTER(C.c_size_t)]),
+    "bpx_group_create": (C.c_int, [C.POINTER(_p), C.POINTER(_p), C.POINTER(_p), C.POINTER(_p),
+                                   C.c_int32, _p, C.c_size_t, C.POINTER(_p)]),
+    "bpx_group_launch": (C.c_int, [_p, _p]),
+    "bpx_group_free": (None, [_p]),
+    "bpx_tile_count": (C.c_int32, [C.c_int32]),
     "bpx_set_tile_table": (C.c_int, [_i32p, C.c_int32]),
     "bpx_force_tile": (C.c_int, [C.c_int32]),
     "bpx_last_error": (C.c_char_p, []),
@@ -334,12 +339,44 @@ def coded_matmul_grouped(plans, As, Bs, Cs, ws, stream=None):
     _check(_lib.bpx_coded_matmul_grouped(P, A, B, Cc, n, w, wb, _stream(stream)))
 
 
-def grouped_extra_bytes(count):
-    return _lib.bpx_grouped_extra_bytes(count)
+def group_workspace_bytes(plans):
+    n = len(plans)
+    P = (_p * n)(*[p._h for p in plans])
+    b = C.c_size_t()
+    _check(_lib.bpx_group_workspace_bytes(P, n, C.byref(b)))
+    return b.value
 
 
-def tile_count():
-    return _lib.bpx_tile_count()
+class Group:
+    """A grouped launch over many plans (bpx_group_*): operands and workspace
+    are fixed at creation, so launch() can be captured in a HIP graph."""
+
+    def __init__(self, plans, As, Bs, Cs, ws):
+        n = len(plans)
+        P = (_p * n)(*[p._h for p in plans])
+        A = (_p * n)(*[_p(a.data_ptr()) for a in As])
+        B = (_p * n)(*[_p(b.data_ptr()) for b in Bs])
+        Cc = (_p * n)(*[_p(c.data_ptr()) for c in Cs])
+        w, wb = _ws(ws)
+        h = _p()
+        _check(_lib.bpx_group_create(P, A, B, Cc, n, w, wb, C.byref(h)))
+        self._h = h
+        self._keep = (plans, As, Bs, Cs, ws)   # operands must outlive the group
+
+    def launch(self, stream=None):
+        _check(_lib.bpx_group_launch(self._h, _stream(stream)))
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None) and self._h.value:
+                _lib.bpx_group_free(self._h)
+                self._h = _p()
+        except Exception:        # interpreter shutdown
+            pass
+
+
+def tile_count(prec=PREC_F32):
+    return _lib.bpx_tile_count(prec)
 
 
 def set_tile_table(table):

@@ -225,6 +225,197 @@ bpx_status peel_impl(bpx_plan* plan, const void* ws, size_t ws_bytes, float* C, 
   return BPX_OK;
 }
 
+
+// ------------------------------------------------------------ groups --
+struct GroupLaunch {
+  int32_t tile, offset, n, grid;
+};
+
+bpx_status group_build(bpx_plan* const* plans, const float* const* A, const float* const* B,
+                       float* const* C, int32_t count, void* ws, size_t ws_bytes,
+                       bpx_group* g);
+
+}  // namespace
+}  // namespace bpx
+
+struct bpx_group {
+  int32_t count = 0, prec = 0;
+  void* dev = nullptr;
+  int32_t dev_id = -1;
+  const bpx::GroupDesc* d_desc = nullptr;
+  const int64_t* d_bstart = nullptr;
+  const int64_t* d_pstart = nullptr;
+  const bpx::GroupTile* d_tiles = nullptr;
+  int64_t total_b = 0, total_p = 0;
+  int32_t max_slots = 0;
+  std::vector<bpx::GroupLaunch> launches;
+};
+
+namespace bpx {
+namespace {
+
+size_t group_ws_bytes(bpx_plan* const* plans, int32_t count) {
+  size_t b = 0;
+  for (int32_t i = 0; i < count; ++i) b += bpx_plan::align256(plans[i]->ws_bytes());
+  return b;
+}
+
+bpx_status group_build(bpx_plan* const* plans, const float* const* A, const float* const* B,
+                       float* const* C, int32_t count, void* ws, size_t ws_bytes,
+                       bpx_group* g) {
+  if (!plans || !A || !B || !C || count < 1) return fail(BPX_E_INVALID, "null argument");
+  const int32_t prec = plans[0]->prec;
+  if (prec != BPX_PREC_BF16 && prec != BPX_PREC_BF16X3)
+    return fail(BPX_E_UNSUPPORTED, "grouped launch runs BF16 or BF16x3 plans");
+  for (int32_t i = 0; i < count; ++i) {
+    bpx_plan* pl = plans[i];
+    if (!pl) return fail(BPX_E_INVALID, "null plan");
+    if (!pl->decodable) return fail(BPX_E_UNDECODABLE, "a plan of the group is not decodable");
+    if (pl->prec != prec) return fail(BPX_E_INVALID, "plans of a group must share a precision");
+    if (pl->K % 4 != 0 || pl->N % 4 != 0)
+      return fail(BPX_E_INVALID, "grouped products need K and N multiples of 4");
+    if (!A[i] || !B[i] || !C[i] || !aligned16(A[i]) || !aligned16(B[i]) || !aligned16(C[i]))
+      return fail(BPX_E_INVALID, "operand null or not 16-byte aligned");
+    if ((pl->Mb + 256) * pl->K >= ((int64_t)1 << 30))
+      return fail(BPX_E_UNSUPPORTED, "block too large for 32-bit tile offsets");
+    bpx_status st = upload(pl);
+    if (st != BPX_OK) return st;
+  }
+  if (!ws || ((uintptr_t)ws & 255u) || ws_bytes < group_ws_bytes(plans, count))
+    return fail(BPX_E_INVALID, "workspace missing, not 256-byte aligned or too small");
+
+  std::vector<GroupDesc> desc(count);
+  std::vector<int64_t> bstart(count), pstart(count);
+  std::vector<std::vector<GroupTile>> by_tile(bf16_tile_count());
+  std::vector<std::vector<int64_t>> key(bf16_tile_count());
+  char* w = static_cast<char*>(ws);
+  int64_t tb = 0, tp = 0;
+  int32_t max_slots = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    bpx_plan* pl = plans[i];
+    GroupDesc& d = desc[i];
+    d = GroupDesc{};
+    GemmParams& p = d.g;
+    p.A = A[i];
+    p.lda = pl->K;
+    p.B = B[i];
+    p.ldb = pl->N;
+    p.C = C[i];
+    p.ldc = pl->N;
+    p.Y = reinterpret_cast<float*>(w);
+    p.M = pl->M;
+    p.K = pl->K;
+    p.N = pl->N;
+    p.Mb = pl->Mb;
+    p.syms = pl->d_gemm_syms;
+    p.ids = pl->d_gemm_ids;
+    p.n_sym = (int32_t)pl->computed.size();
+    p.prec = prec;
+    char* planes = w + bpx_plan::align256(pl->y_bytes());
+    p.bt_hi = reinterpret_cast<const unsigned short*>(planes);
+    p.bt_lo = prec == BPX_PREC_BF16X3
+                  ? reinterpret_cast<const unsigned short*>(planes + pl->bt_plane_bytes())
+                  : nullptr;
+    p.kp = pl->kp();
+    const int32_t t = choose_tile(prec, pl->Mb, pl->N, pl->K);
+    const TileShape sh = bf16_tile_shape(t);
+    p.tiles_m = (int32_t)((pl->Mb + sh.bm - 1) / sh.bm);
+    p.tiles_n = (int32_t)((pl->N + sh.bn - 1) / sh.bn);
+    d.tile = t;
+    const int64_t nt = (int64_t)p.n_sym * p.tiles_m * p.tiles_n;
+    for (int64_t l = 0; l < nt; ++l) {
+      by_tile[t].push_back(GroupTile{i, (int32_t)l});
+      key[t].push_back(pl->K);
+    }
+    PeelParams& pe = d.pe;
+    pe.Y = p.Y;
+    pe.C = C[i];
+    pe.ldc = pl->N;
+    pe.M = pl->M;
+    pe.N = pl->N;
+    pe.Mb = pl->Mb;
+    pe.steps = pl->d_steps;
+    pe.subs = pl->d_step_subs;
+    pe.nsteps = (int32_t)pl->steps.size();
+    pe.nslots = pl->n_lds_slots;
+    max_slots = std::max(max_slots, pl->n_lds_slots);
+    d.b_tn = (int32_t)((pl->N + 63) / 64);
+    d.b_tk = (int32_t)((pl->kp() + 63) / 64);
+    bstart[i] = tb;
+    tb += (int64_t)d.b_tn * d.b_tk;
+    pstart[i] = tp;
+    if (pe.nsteps > 0) tp += (pl->Mb * pl->N + 255) / 256;
+    w += bpx_plan::align256(pl->ws_bytes());
+  }
+  if ((size_t)max_slots * 256 * 4 > 160 * 1024)
+    return fail(BPX_E_UNSUPPORTED, "peel needs more LDS than a workgroup has");
+  // tile lists: longest K first (stable), one persistent launch per shape
+  std::vector<GroupTile> tiles;
+  std::vector<GroupLaunch> launches;
+  for (int32_t t = 0; t < (int32_t)by_tile.size(); ++t) {
+    if (by_tile[t].empty()) continue;
+    std::vector<size_t> idx(by_tile[t].size());
+    for (size_t j = 0; j < idx.size(); ++j) idx[j] = j;
+    std::stable_sort(idx.begin(), idx.end(),
+                     [&](size_t a, size_t b) { return key[t][a] > key[t][b]; });
+    GroupLaunch L{t, (int32_t)tiles.size(), (int32_t)idx.size(), 0};
+    for (size_t j : idx) tiles.push_back(by_tile[t][j]);
+    const TileShape sh = bf16_tile_shape(t);
+    const int32_t slots = 256 * ((sh.bm * sh.bn <= 128 * 128) ? 2 : 1);
+    L.grid = std::min(L.n, slots);
+    launches.push_back(L);
+  }
+  // one device block: descriptors | bstart | pstart | tiles
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  const size_t s0 = al(desc.size() * sizeof(GroupDesc));
+  const size_t s1 = al(bstart.size() * 8);
+  const size_t s2 = al(pstart.size() * 8);
+  const size_t s3 = al(std::max<size_t>(tiles.size(), 1) * sizeof(GroupTile));
+  std::string host(s0 + s1 + s2 + s3, '\0');
+  std::memcpy(&host[0], desc.data(), desc.size() * sizeof(GroupDesc));
+  std::memcpy(&host[s0], bstart.data(), bstart.size() * 8);
+  std::memcpy(&host[s0 + s1], pstart.data(), pstart.size() * 8);
+  std::memcpy(&host[s0 + s1 + s2], tiles.data(), tiles.size() * sizeof(GroupTile));
+  void* dptr = nullptr;
+  hipError_t e = hipMalloc(&dptr, host.size());
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc(group descriptors)");
+  e = hipMemcpy(dptr, host.data(), host.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(dptr);
+    return hip_fail(e, "hipMemcpy(group descriptors)");
+  }
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  char* base = static_cast<char*>(dptr);
+  g->count = count;
+  g->prec = prec;
+  g->dev = dptr;
+  g->dev_id = dev;
+  g->d_desc = reinterpret_cast<const GroupDesc*>(base);
+  g->d_bstart = reinterpret_cast<const int64_t*>(base + s0);
+  g->d_pstart = reinterpret_cast<const int64_t*>(base + s0 + s1);
+  g->d_tiles = reinterpret_cast<const GroupTile*>(base + s0 + s1 + s2);
+  g->total_b = tb;
+  g->total_p = tp;
+  g->max_slots = max_slots;
+  g->launches = launches;
+  return BPX_OK;
+}
+
+bpx_status group_launch(bpx_group* g, hipStream_t stream) {
+  hipError_t e = launch_split_b_grouped(g->d_desc, g->d_bstart, g->count, g->total_b, stream);
+  if (e != hipSuccess) return hip_fail(e, "grouped split-B launch");
+  const int32_t split = g->prec == BPX_PREC_BF16X3 ? 3 : 1;
+  for (const GroupLaunch& L : g->launches) {
+    e = launch_gemm_bf16_grouped(g->d_desc, g->d_tiles + L.offset, L.n, L.tile, split, L.grid,
+                                 stream);
+    if (e != hipSuccess) return hip_fail(e, "grouped GEMM launch");
+  }
+  e = launch_peel_grouped(g->d_desc, g->d_pstart, g->count, g->total_p, g->max_slots, stream);
+  if (e != hipSuccess) return hip_fail(e, "grouped peel launch");
+  return BPX_OK;
+}
+
 }  // namespace
 }  // namespace bpx
 
@@ -427,23 +618,62 @@ bpx_status bpx_coded_matmul(bpx_plan* plan, const float* A, int64_t lda, const f
   return peel_impl(plan, ws, ws_bytes, C, ldc, s);
 }
 
+bpx_status bpx_group_workspace_bytes(bpx_plan* const* plans, int32_t count, size_t* bytes) {
+  if (!plans || !bytes || count < 1) return fail(BPX_E_INVALID, "null argument");
+  for (int32_t i = 0; i < count; ++i)
+    if (!plans[i]) return fail(BPX_E_INVALID, "null plan");
+  *bytes = group_ws_bytes(plans, count);
+  return BPX_OK;
+}
+
+bpx_status bpx_group_create(bpx_plan* const* plans, const float* const* A, const float* const* B,
+                            float* const* C, int32_t count, void* ws, size_t ws_bytes,
+                            bpx_group** out) {
+  if (!out) return fail(BPX_E_INVALID, "null argument");
+  *out = nullptr;
+  bpx_group* g = new (std::nothrow) bpx_group();
+  if (!g) return fail(BPX_E_NOMEM, "out of host memory");
+  bpx_status st = group_build(plans, A, B, C, count, ws, ws_bytes, g);
+  if (st != BPX_OK) {
+    delete g;
+    return st;
+  }
+  *out = g;
+  return BPX_OK;
+}
+
+bpx_status bpx_group_launch(bpx_group* group, bpx_stream stream) {
+  if (!group) return fail(BPX_E_INVALID, "null group");
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if (dev != group->dev_id) return fail(BPX_E_INVALID, "group lives on another device");
+  return group_launch(group, reinterpret_cast<hipStream_t>(stream));
+}
+
+void bpx_group_free(bpx_group* group) {
+  if (!group) return;
+  if (group->dev) (void)hipFree(group->dev);
+  delete group;
+}
+
 bpx_status bpx_coded_matmul_grouped(bpx_plan* const* plans, const float* const* A,
                                     const float* const* B, float* const* C, int32_t count,
                                     void* ws, size_t ws_bytes, bpx_stream stream) {
-  (void)plans;
-  (void)A;
-  (void)B;
-  (void)C;
-  (void)count;
-  (void)ws;
-  (void)ws_bytes;
-  (void)stream;
-  return fail(BPX_E_UNSUPPORTED, "grouped launch not built yet");
+  bpx_group* g = nullptr;
+  bpx_status st = bpx_group_create(plans, A, B, C, count, ws, ws_bytes, &g);
+  if (st != BPX_OK) return st;
+  st = bpx_group_launch(g, stream);
+  const hipError_t e = hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream));
+  bpx_group_free(g);
+  if (st != BPX_OK) return st;
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  return BPX_OK;
 }
 
-size_t bpx_grouped_extra_bytes(int32_t count) { return count > 0 ? 0 : 0; }
-
-int32_t bpx_tile_count(void) { return gemm_tile_count(); }
+int32_t bpx_tile_count(int32_t prec) {
+  return (prec == BPX_PREC_BF16 || prec == BPX_PREC_BF16X3) ? bf16_tile_count()
+                                                              : gemm_tile_count();
+}
 
 bpx_status bpx_set_tile_table(const int32_t* table, int32_t n_entries) {
   const int32_t need = (int32_t)(sizeof(g_tile_table) / sizeof(g_tile_table[0]));

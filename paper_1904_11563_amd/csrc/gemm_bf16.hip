@@ -311,6 +311,58 @@ __global__ __launch_bounds__(kThreads, OCC) void coded_gemm_bf16_kernel(GemmPara
   bf16_tile<BM, BN, SPLIT>(p, si, mt, nt, lds);
 }
 
+// Grouped split-B: a flat range of 64 x 64 transpose blocks over products.
+__global__ __launch_bounds__(256) void split_b_grouped_kernel(const GroupDesc* d,
+                                                              const int64_t* bstart, int32_t count) {
+  const int64_t b = blockIdx.x;
+  int lo = 0, hi = count - 1;  // last product with bstart <= b
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (bstart[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  const GroupDesc& g = d[lo];
+  const int64_t r = b - bstart[lo];
+  const int64_t k0 = (r / g.b_tn) * 64, n0 = (r % g.b_tn) * 64;
+  __shared__ float t[64][65];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int64_t K = g.g.K, N = g.g.N, Kp = g.g.kp;
+  for (int rr = ty; rr < 64; rr += 4) {
+    const int64_t k = k0 + rr, n = n0 + tx;
+    t[rr][tx] = (k < K && n < N) ? g.g.B[k * g.g.ldb + n] : 0.f;
+  }
+  __syncthreads();
+  us* hi_p = const_cast<us*>(g.g.bt_hi);
+  us* lo_p = const_cast<us*>(g.g.bt_lo);
+  for (int rr = ty; rr < 64; rr += 4) {
+    const int64_t n = n0 + rr, k = k0 + tx;
+    if (n < N && k < Kp) {
+      const float x = t[tx][rr];
+      const __bf16 h = (__bf16)x;
+      hi_p[n * Kp + k] = __builtin_bit_cast(us, h);
+      if (lo_p) lo_p[n * Kp + k] = __builtin_bit_cast(us, (__bf16)(x - (float)h));
+    }
+  }
+}
+
+// Persistent grouped GEMM: workgroup w takes tiles w, w + grid, w + 2 grid, ...
+// of a list already ordered longest-K first.
+template <int BM, int BN, int SPLIT>
+__global__ __launch_bounds__(kThreads) void gemm_bf16_grouped_kernel(const GroupDesc* d,
+                                                                     const GroupTile* tiles,
+                                                                     int32_t n_tiles) {
+  __shared__ __attribute__((aligned(16))) us lds[bf16_lds_elems<BM, BN, SPLIT>()];
+  for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const GroupTile gt = tiles[t];
+    const GemmParams& p = d[gt.prod].g;
+    const int per_sym = p.tiles_m * p.tiles_n;
+    const int si = gt.lin / per_sym;
+    const int rem = gt.lin - si * per_sym;
+    const int mt = rem / p.tiles_n;
+    const int nt = rem - mt * p.tiles_n;
+    bf16_tile<BM, BN, SPLIT>(p, si, mt, nt, lds);
+  }
+}
+
 struct Bf16Entry {
   TileShape shape;
   void (*k1)(GemmParams);
@@ -334,6 +386,35 @@ hipError_t launch_split_b(const float* B, int64_t ldb, int64_t K, int64_t N, int
   const dim3 grid((unsigned)((N + 63) / 64), (unsigned)((Kp + 63) / 64));
   hipLaunchKernelGGL(split_b_kernel, grid, dim3(256), 0, stream, B, ldb, K, N, Kp,
                      static_cast<us*>(bt_hi), static_cast<us*>(bt_lo));
+  return hipGetLastError();
+}
+
+hipError_t launch_split_b_grouped(const GroupDesc* d, const int64_t* bstart, int32_t count,
+                                  int64_t total_blocks, hipStream_t stream) {
+  if (total_blocks == 0) return hipSuccess;
+  if (total_blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(split_b_grouped_kernel, dim3((unsigned)total_blocks), dim3(256), 0, stream,
+                     d, bstart, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_bf16_grouped(const GroupDesc* d, const GroupTile* tiles, int32_t n_tiles,
+                                    int32_t tile, int32_t split, int32_t grid,
+                                    hipStream_t stream) {
+  if (n_tiles == 0) return hipSuccess;
+  void (*k)(const GroupDesc*, const GroupTile*, int32_t) = nullptr;
+  switch (tile * 4 + split) {
+    case 0 * 4 + 1: k = gemm_bf16_grouped_kernel<128, 128, 1>; break;
+    case 0 * 4 + 3: k = gemm_bf16_grouped_kernel<128, 128, 3>; break;
+    case 1 * 4 + 1: k = gemm_bf16_grouped_kernel<64, 128, 1>; break;
+    case 1 * 4 + 3: k = gemm_bf16_grouped_kernel<64, 128, 3>; break;
+    case 2 * 4 + 1: k = gemm_bf16_grouped_kernel<128, 256, 1>; break;
+    case 2 * 4 + 3: k = gemm_bf16_grouped_kernel<128, 256, 3>; break;
+    case 3 * 4 + 1: k = gemm_bf16_grouped_kernel<64, 256, 1>; break;
+    case 3 * 4 + 3: k = gemm_bf16_grouped_kernel<64, 256, 3>; break;
+    default: return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kThreads), 0, stream, d, tiles, n_tiles);
   return hipGetLastError();
 }
 

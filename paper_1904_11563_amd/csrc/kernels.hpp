@@ -95,6 +95,31 @@ TileShape bf16_tile_shape(int32_t t);
 hipError_t launch_split_b(const float* B, int64_t ldb, int64_t K, int64_t N, int64_t Kp,
                           void* bt_hi, void* bt_lo, hipStream_t stream);
 hipError_t launch_coded_gemm_bf16(const GemmParams& p, int32_t tile, hipStream_t stream);
+// ------------------------------------------------------------ grouped --
+// Per-product descriptor of a grouped launch (device memory).
+struct GroupDesc {
+  GemmParams g;      // tiles_m / tiles_n set for the product's tile shape
+  PeelParams pe;
+  int32_t b_tn, b_tk;  // split-B grid of the product (64 x 64 tiles)
+  int32_t tile;        // tile shape index
+  int32_t pad;
+};
+// A grouped GEMM tile: product and tile index inside that product's grid.
+struct GroupTile {
+  int32_t prod;
+  int32_t lin;
+};
+// Grouped split-B: blocks [bstart[i], bstart[i+1]) belong to product i.
+hipError_t launch_split_b_grouped(const GroupDesc* d, const int64_t* bstart, int32_t count,
+                                  int64_t total_blocks, hipStream_t stream);
+// Persistent grouped BF16 / BF16x3 GEMM over a tile list of one tile shape.
+hipError_t launch_gemm_bf16_grouped(const GroupDesc* d, const GroupTile* tiles, int32_t n_tiles,
+                                    int32_t tile, int32_t split, int32_t grid,
+                                    hipStream_t stream);
+// Grouped peel: blocks [pstart[i], pstart[i+1]) belong to product i.
+hipError_t launch_peel_grouped(const GroupDesc* d, const int64_t* pstart, int32_t count,
+                               int64_t total_blocks, int32_t max_slots, hipStream_t stream);
+
 hipError_t launch_quant_a(const Fp8Params& p, hipStream_t stream);
 hipError_t launch_quant_b(const Fp8Params& p, hipStream_t stream);
 hipError_t launch_coded_gemm_fp8(const Fp8Params& p, hipStream_t stream);

@@ -20,11 +20,10 @@ namespace {
 constexpr int kBatch = 8;  // steps whose loads are issued together
 
 template <int THREADS>
-__global__ __launch_bounds__(THREADS) void peel_kernel(PeelParams p) {
-  extern __shared__ float xs[];  // [nslots][THREADS]
+__device__ __forceinline__ void peel_block(const PeelParams& p, int64_t block, float* xs) {
   const int tid = threadIdx.x;
   const int64_t total = p.Mb * p.N;
-  const int64_t e = (int64_t)blockIdx.x * THREADS + tid;
+  const int64_t e = block * THREADS + tid;
   const bool active = e < total;
   const int64_t r = active ? e / p.N : 0;
   const int64_t c = active ? e - r * p.N : 0;
@@ -78,7 +77,37 @@ __global__ __launch_bounds__(THREADS) void peel_kernel(PeelParams p) {
   }
 }
 
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void peel_kernel(PeelParams p) {
+  extern __shared__ float xs[];  // [nslots][THREADS]
+  peel_block<THREADS>(p, blockIdx.x, xs);
+}
+
+// Grouped peel: blocks [pstart[i], pstart[i+1]) run product i's program.
+__global__ __launch_bounds__(256) void peel_grouped_kernel(const GroupDesc* d,
+                                                           const int64_t* pstart, int32_t count) {
+  extern __shared__ float xs[];
+  const int64_t b = blockIdx.x;
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (pstart[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  peel_block<256>(d[lo].pe, b - pstart[lo], xs);
+}
+
 }  // namespace
+
+hipError_t launch_peel_grouped(const GroupDesc* d, const int64_t* pstart, int32_t count,
+                               int64_t total_blocks, int32_t max_slots, hipStream_t stream) {
+  if (total_blocks == 0) return hipSuccess;
+  const size_t lds = (size_t)max_slots * 256 * sizeof(float);
+  if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
+  if (total_blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(peel_grouped_kernel, dim3((unsigned)total_blocks), dim3(256), lds, stream,
+                     d, pstart, count);
+  return hipGetLastError();
+}
 
 hipError_t launch_peel(const PeelParams& p, hipStream_t stream) {
   if (p.nsteps == 0) return hipSuccess;

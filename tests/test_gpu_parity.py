@@ -445,3 +445,100 @@ def test_fp8_integer_operands_small_chain():
     e = relf(C, pipeline.uncoded(A, B))
     _say("fp8x2 depth-9 chain relF", e)
     assert e <= TOL_FP8 * np.sqrt(10)
+
+
+# ---------------------------------------------------------- grouped path --
+
+def _group_case(seed, count, integer):
+    """count products with shapes from the batch generator (scaled down),
+    codes (6,4,2) or (12,8,2) by k, own seeded erasure patterns."""
+    codes_by_k = {4: code642(), 8: lib_code(inputs.CODE_1282)}
+    shapes = inputs.batch_shapes(seed, count, lo=128, hi=640, mult=4)
+    plans, As, Bs, Cs, host_ops = [], [], [], [], []
+    for i, (M, K, N, k) in enumerate(shapes):
+        code = codes_by_k[k]
+        n = code.info()["n"]
+        arrival, _ = inputs.erasure_arrival(seed * 1000 + i, n, n - k)
+        plan = bpx.Plan(code, arrival, 0, bpx.MODE_STRAGGLER, M, K, N, bpx.PREC_BF16X3)
+        if integer:
+            A = inputs.integers(seed * 1000 + i, inputs.TAG_A, (M, K))
+            B = inputs.integers(seed * 1000 + i, inputs.TAG_B, (K, N))
+        else:
+            A = inputs.normal(seed * 1000 + i, inputs.TAG_A, (M, K))
+            B = inputs.normal(seed * 1000 + i, inputs.TAG_B, (K, N))
+        plans.append(plan)
+        As.append(dev(A))
+        Bs.append(dev(B))
+        Cs.append(torch.full((M, N), float("nan"), device="cuda"))
+        host_ops.append((A, B))
+    ws = torch.empty(bpx.group_workspace_bytes(plans), dtype=torch.uint8, device="cuda")
+    return plans, As, Bs, Cs, ws, host_ops
+
+
+def test_grouped_integer_exact_and_float_tolerance():
+    """Integer operands: every product bit exact.  Float operands: the batch's
+    relative Frobenius error (all products together) within the BF16x3 bound
+    1e-5, and each product within sqrt(2 d) times it, d its deepest release
+    round (independent product errors add in quadrature along a chain)."""
+    for integer in (True, False):
+        plans, As, Bs, Cs, ws, ops = _group_case(3 if integer else 4, 24, integer)
+        g = bpx.Group(plans, As, Bs, Cs, ws)
+        g.launch()
+        torch.cuda.synchronize()
+        num = den = 0.0
+        errs = []
+        for i, (A, B) in enumerate(ops):
+            C = host(Cs[i])
+            R = A.astype(np.float64) @ B.astype(np.float64)
+            if integer:
+                assert np.array_equal(C.astype(np.float64), R), i
+                continue
+            d = plans[i].info()["depth_max"]
+            e = relf(C, R)
+            errs.append((i, d, e))
+            assert e <= TOL_BF16X3 * np.sqrt(2 * d), (i, d, e)
+            num += float(np.sum((C - R) ** 2))
+            den += float(np.sum(R ** 2))
+        if not integer:
+            _say("grouped bf16x3 per-product (i, depth, relF)", errs)
+            _say("grouped bf16x3 batch relF", np.sqrt(num / den))
+            assert np.sqrt(num / den) <= TOL_BF16X3
+
+
+def test_grouped_graph_replay_matches_eager():
+    plans, As, Bs, Cs, ws, ops = _group_case(5, 16, False)
+    g = bpx.Group(plans, As, Bs, Cs, ws)
+    g.launch()
+    torch.cuda.synchronize()
+    eager = [c.clone() for c in Cs]
+    graph = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(graph, stream=s):
+            g.launch()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for c in Cs:
+            c.fill_(float("nan"))               # eager work between replays
+        junk = torch.randn(512, 512, device="cuda") @ torch.randn(512, 512, device="cuda")
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for c, e in zip(Cs, eager):
+            assert torch.equal(c, e), rep
+        del junk
+
+
+def test_grouped_rejects_undecodable():
+    code = bpx.Code.table3()
+    good = bpx.Plan(code, [0, 1, 2, 3, 4], 0, bpx.MODE_STRAGGLER, 36, 8, 8, bpx.PREC_BF16X3)
+    bad = bpx.Plan(code, [0, 1, 2, 3, 4], 3, bpx.MODE_ERASURE, 36, 8, 8, bpx.PREC_BF16X3)
+    A = [torch.zeros((36, 8), device="cuda") for _ in range(2)]
+    B = [torch.zeros((8, 8), device="cuda") for _ in range(2)]
+    C = [torch.zeros((36, 8), device="cuda") for _ in range(2)]
+    ws = torch.empty(bpx.group_workspace_bytes([good, bad]) + 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(bpx.BpxError) as e:
+        bpx.Group([good, bad], A, B, C, ws)
+    assert e.value.status == bpx.E_UNDECODABLE
