@@ -1,12 +1,19 @@
 """Benchmark: useful TFLOP/s of the coded product (encode + coded GEMM + peel).
 
-One step = one full coded product C = A.B on the workload: the encode fused
-into the coded GEMM launch, then the peel launch, with A, B and the plan
-already resident on the GPU.  Useful FLOPs are 2*M*N*K whatever the
-redundancy.  The uncoded product on the same operands is timed beside it
-(the same GEMM kernel with the identity code, and torch.matmul), the
-coded GEMM launch is timed on its own for the roofline, and the float64
-oracle is timed on the host for a bounded sample of the same workload.
+Default workload (the headline): FP32, A 8192x8192, B 8192x4096 N(0,1), the
+(12,8,4) array code, shifted-exponential worker times; the decode uses the
+first arrived columns that peel, and every symbol of those columns is
+computed.  One step = one whole coded product: the coded-GEMM launch (encode
+fused into its A loads) and the peel launch, operands already resident on
+the GPU.  Useful FLOPs are 2*M*N*K whatever the redundancy.
+
+Beside it: the same kernels on the identity code (uncoded), torch.matmul on
+the same operands, the dominant kernel's roofline from HIP events over the
+timed region, and the float64 oracle on the host for a bounded sample.
+
+Other workloads (--workload): fp32_small, bf16_small (split-BF16x3),
+fp8_mojette (FP8x2, Mojette code), batch (256 uneven products, one grouped
+launch sequence captured in a HIP graph).
 
 Prints ONE JSON line.
 """
@@ -20,8 +27,11 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0, "fp8": 5000.0, "fp8x2": 5000.0}
-HBM_PEAK_GBS = 8000.0
+# MI355X dense peaks (TFLOP/s).  A split-BF16x3 product issues 3 BF16 MFMA
+# passes and FP8x2 two FP8 passes per useful flop, so their effective peaks
+# are the BF16 / FP8 peak divided by 3 / 2.
+PEAK = {"f32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0 / 3, "fp8": 5000.0, "fp8x2": 2500.0}
+METRIC = "useful TFLOP/s of coded A.B (encode+GEMM+peel) vs uncoded GEMM at stated rel err"
 
 
 def parse():
@@ -29,17 +39,21 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="fp32_scale")
-    ap.add_argument("--mode", default="straggler", choices=["straggler", "full", "min"])
+    ap.add_argument("--workload", default="fp32_scale",
+                    choices=["fp32_scale", "fp32_small", "bf16_small", "fp8_mojette", "batch"])
+    ap.add_argument("--prec", default=None, help="override the workload's precision")
+    ap.add_argument("--mode", default="arrival", choices=["arrival", "full", "min"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-ref", action="store_true", help="skip the uncoded references")
-    ap.add_argument("--cpu-cols", type=int, default=256,
-                    help="columns of B in the CPU oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="rough budget of the CPU oracle sample")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (for scaling HBM counters)")
     return ap.parse_args()
 
 
-def gemm_source_hash():
+def kernel_source_hash():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1904_11563_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
@@ -49,72 +63,85 @@ def gemm_source_hash():
 
 
 def load_traffic(workload, prec):
-    """HBM bytes per coded-GEMM launch from the committed rocprofv3 counter
-    summary, or None when it is missing or the GEMM sources changed since."""
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, or None if missing or taken on other sources."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
-        d = json.load(open(path))
-        e = d[f"{workload}:{prec}"]
-        if e.get("gemm_source") != gemm_source_hash():
+        e = json.load(open(path))[f"{workload}:{prec}"]
+        if e.get("gemm_source") != kernel_source_hash():
             return None
         return e["bytes_per_launch"]
     except Exception:
         return None
 
 
-def cpu_baseline(A, B, ocode, ref_plan, cols):
-    """The float64 oracle on the first `cols` columns of B (same A, same code
-    and schedule): useful GFLOP/s on the host cores."""
-    import numpy as np
-
-    from oracle import pipeline
+def blas_threads():
     try:
         from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        return max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
-        threads = len(os.sched_getaffinity(0))
-    Bs = np.ascontiguousarray(B[:, :cols])
-    t0 = time.perf_counter()
-    C = pipeline.coded_matmul_ref(A, Bs, ocode, ref_plan)
-    dt = time.perf_counter() - t0
-    M, K = A.shape
-    useful = 2.0 * M * K * cols
-    return {"value": useful / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"float64 oracle coded pipeline (encode, {len(ref_plan.computed)} coded "
-                      f"products, peel) on A {M}x{K} and the first {cols} of B's columns; "
-                      f"{dt:.1f} s", "seconds": dt}, C
+        return len(os.sched_getaffinity(0))
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
-                          "n_gpus": args.gpus}), flush=True)
-        sys.exit(2)
+def timed(torch, fn, steps, stream=None):
+    """Mean milliseconds of fn over `steps` calls (events on the stream)."""
+    s = stream or torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(steps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
 
+
+def build_code(bpx, spec):
+    if spec.kind == "search":
+        return bpx.Code.search(spec.n, spec.k, spec.b, spec.sigma, spec.seed, spec.restarts,
+                               spec.iters)
+    return bpx.Code.mojette(spec.k, spec.b, spec.n, spec.qe)
+
+
+def oracle_code(code):
+    from oracle import codes as ocodes
+    inf = code.info()
+    return ocodes.Code("array", inf["n"], inf["k"], inf["b"], code.columns())
+
+
+def header(args, value, ms, prec, config):
+    return {"metric": METRIC, "value": value, "unit": "TFLOP/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": prec,
+            "data": "synthetic", "config": config}
+
+
+# ----------------------------------------------------------- single product --
+
+def run_single(args):
     import numpy as np
     import torch
 
-    from paper_1904_11563_amd import bpx, inputs
+    from paper_1904_11563_amd import autotune, bpx, inputs
 
+    autotune.load()
     w = inputs.WORKLOADS[args.workload]
-    prec = bpx.PREC_NAMES[w.prec]
+    prec_name = args.prec or ("fp8x2" if w.prec == "fp8" else w.prec)
+    prec = bpx.PREC_NAMES[prec_name]
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-
     spec = w.code
     t0 = time.perf_counter()
-    if spec.kind == "search":
-        code = bpx.Code.search(spec.n, spec.k, spec.b, spec.sigma, spec.seed, spec.restarts,
-                               spec.iters)
-    else:
-        code = bpx.Code.mojette(spec.k, spec.b, spec.n, spec.qe)
+    code = build_code(bpx, spec)
     code_s = time.perf_counter() - t0
     arrival, lost, mode_name = inputs.arrival_of(w, seed=args.seed)
-    mode = {"straggler": bpx.MODE_STRAGGLER if mode_name == "straggler" else bpx.MODE_ERASURE,
-            "full": bpx.MODE_FULL, "min": bpx.MODE_MIN}[args.mode]
+    if args.mode == "full":
+        mode = bpx.MODE_FULL
+    elif args.mode == "min":
+        mode = bpx.MODE_MIN
+    else:
+        mode = bpx.MODE_STRAGGLER if mode_name == "straggler" else bpx.MODE_ERASURE
     t0 = time.perf_counter()
     plan = bpx.Plan(code, arrival, lost, mode, w.M, w.K, w.N, prec)
     plan_us = (time.perf_counter() - t0) * 1e6
@@ -131,16 +158,12 @@ def main():
     ws = bpx.alloc_workspace(plan, dev)
     stream = torch.cuda.current_stream()
 
-    def step():
-        bpx.coded_matmul(plan, Ad, Bd, Cd, ws)
-
     for _ in range(args.warmup):
-        step()
+        bpx.coded_matmul(plan, Ad, Bd, Cd, ws)
     torch.cuda.synchronize()
 
-    # timed region: K whole steps
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
-           torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    # timed region: K whole steps; events split each step into its launches
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for e0, e1, e2 in ev:
@@ -153,85 +176,277 @@ def main():
     wall = time.perf_counter() - t_start
     gemm_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in ev]))
     peel_ms = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
-    step_ms = float(np.mean([a.elapsed_time(c) for a, _, c in ev]))
-    ms_per_step = wall * 1e3 / args.steps
+    ms = wall * 1e3 / args.steps
 
     useful = 2.0 * w.M * w.N * w.K
-    value = useful / (ms_per_step * 1e-3) / 1e12
+    value = useful / (ms * 1e-3) / 1e12
 
-    # correctness on sampled rows against float64
+    # error on sampled rows (up to four per data block, about 256 in all)
+    # against float64
     Mb = info["Mb"]
     kb = spec.k * spec.b
+    per = max(1, min(4, 256 // kb))
     rows = np.unique(np.concatenate([np.arange(s * Mb, min((s + 1) * Mb, w.M),
-                                               max(1, Mb // 4)) for s in range(kb)]))
+                                               max(1, Mb // per))[:per] for s in range(kb)]))
     C = Cd.cpu().numpy()
     R = A[rows].astype(np.float64) @ B.astype(np.float64)
     rel_err = float(np.linalg.norm(C[rows] - R) / np.linalg.norm(R))
 
-    # uncoded references on the same operands
     refs = {}
     if not args.no_ref:
+        ref_prec = bpx.PREC_BF16 if prec_name.startswith("fp8") else prec
         ident = bpx.Code.identity(spec.k, spec.b)
-        uplan = bpx.Plan(ident, list(range(spec.k)), 0, bpx.MODE_STRAGGLER, w.M, w.K, w.N, prec)
+        uplan = bpx.Plan(ident, list(range(spec.k)), 0, bpx.MODE_STRAGGLER, w.M, w.K, w.N,
+                         ref_prec)
         uplan.upload()
+        uws = bpx.alloc_workspace(uplan, dev)
         Cu = torch.empty_like(Cd)
         for _ in range(3):
-            bpx.coded_matmul(uplan, Ad, Bd, Cu, None)
+            bpx.coded_matmul(uplan, Ad, Bd, Cu, uws)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for _ in range(args.steps):
-            bpx.coded_matmul(uplan, Ad, Bd, Cu, None)
+            bpx.coded_matmul(uplan, Ad, Bd, Cu, uws)
         torch.cuda.synchronize()
         refs["uncoded_own_tflops"] = useful / ((time.perf_counter() - t1) / args.steps) / 1e12
-        if w.prec == "f32":
+        refs["uncoded_own_prec"] = [k for k, v in bpx.PREC_NAMES.items() if v == ref_prec][0]
+        if prec_name == "f32":
             torch.backends.cuda.matmul.allow_tf32 = False
-            for _ in range(3):
-                torch.matmul(Ad, Bd, out=Cu)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            for _ in range(args.steps):
-                torch.matmul(Ad, Bd, out=Cu)
-            torch.cuda.synchronize()
-            refs["uncoded_torch_tflops"] = useful / ((time.perf_counter() - t1) / args.steps) / 1e12
-        best = max(refs.values())
-        refs["frac_of_uncoded"] = value / best
+            X, Y = Ad, Bd
+            tprec = "f32"
+        else:
+            X, Y = Ad.to(torch.bfloat16), Bd.to(torch.bfloat16)
+            tprec = "bf16"
+        Ct = torch.empty((w.M, w.N), dtype=X.dtype, device=dev)
+        for _ in range(3):
+            torch.matmul(X, Y, out=Ct)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            torch.matmul(X, Y, out=Ct)
+        torch.cuda.synchronize()
+        refs["uncoded_torch_tflops"] = useful / ((time.perf_counter() - t1) / args.steps) / 1e12
+        refs["uncoded_torch_prec"] = tprec
+        refs["frac_of_uncoded_best"] = value / max(refs["uncoded_own_tflops"],
+                                                   refs["uncoded_torch_tflops"])
+        refs["frac_of_uncoded_own"] = value / refs["uncoded_own_tflops"]
 
-    # roofline of the dominant kernel (the coded GEMM)
     n_comp = info["n_computed"]
     gemm_flops = 2.0 * Mb * w.K * w.N * n_comp
     achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[w.prec]
-    roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": load_traffic(w.name, w.prec),
-                "kernel": "coded_gemm", "flops_per_launch": gemm_flops,
-                "launch_ms": gemm_ms}
-
-    out = {
-        "metric": "useful TFLOP/s of coded A.B (encode+GEMM+peel) vs uncoded GEMM at stated rel err",
-        "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": w.prec, "data": "synthetic",
-        "config": {"workload": w.name, "M": w.M, "K": w.K, "N": w.N,
-                   "code": f"{spec.kind}(n={spec.n},k={spec.k},b={spec.b})",
-                   "mode": args.mode if mode_name == "straggler" else "erasure",
-                   "prefix_m": info["prefix_m"], "n_computed": n_comp,
-                   "depth_max": info["depth_max"], "parallelism": "none (1 GPU)"},
-        "rel_err": rel_err,
-        "times_ms": {"step_events": step_ms, "coded_gemm": gemm_ms, "peel": peel_ms,
-                     "plan_host_us": plan_us, "code_build_s": code_s},
-        "roofline": roofline,
-    }
+    kernel = {"f32": "coded_gemm_f32_kernel", "bf16": "split_b + coded_gemm_bf16_kernel",
+              "bf16x3": "split_b + coded_gemm_bf16_kernel",
+              "fp8": "quant_b + quant_a + coded_gemm_fp8_kernel",
+              "fp8x2": "quant_b + quant_a + coded_gemm_fp8_kernel"}[prec_name]
+    roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK[prec_name],
+                "unit": "TFLOP/s", "frac": achieved / PEAK[prec_name],
+                "traffic": load_traffic(w.name, prec_name), "kernel": kernel,
+                "flops_per_launch": gemm_flops, "launch_ms": gemm_ms}
+    cfg = {"workload": w.name, "M": w.M, "K": w.K, "N": w.N,
+           "code": f"{spec.kind}(n={spec.n},k={spec.k},b={spec.b})",
+           "mode": args.mode if args.mode != "arrival" else mode_name,
+           "prefix_m": info["prefix_m"], "n_computed": n_comp, "kb": kb,
+           "depth_max": info["depth_max"], "parallelism": "none (1 GPU)"}
+    out = header(args, value, ms, prec_name, cfg)
+    out.update({"rel_err": rel_err, "rel_err_sample": f"{len(rows)} rows x all columns",
+                "times_ms": {"coded_gemm_call": gemm_ms, "peel": peel_ms,
+                             "plan_host_us": plan_us, "code_build_s": code_s},
+                "roofline": roofline})
     out.update(refs)
     if not args.no_cpu:
-        from oracle import codes as ocodes
-        from oracle.peeling import make_plan
-        cinf = code.info()
-        ocode = ocodes.Code("array", cinf["n"], cinf["k"], cinf["b"], code.columns())
-        ref_plan = make_plan(ocode, list(arrival), lost,
-                             {"straggler": 1 if mode_name == "straggler" else 0,
-                              "full": 2, "min": 3}[args.mode])
-        cb, _ = cpu_baseline(A, B, ocode, ref_plan, min(args.cpu_cols, w.N))
-        out["cpu_baseline"] = cb
+        out["cpu_baseline"] = cpu_single(A, B, code, arrival, lost, mode, w, args.cpu_seconds)
+    return out
+
+
+def cpu_single(A, B, code, arrival, lost, mode, w, budget):
+    """The float64 oracle's coded pipeline on A and the first columns of B,
+    the column count scaled so the run takes about `budget` seconds."""
+    import numpy as np
+
+    from oracle import pipeline
+    from oracle.peeling import make_plan
+    oc = oracle_code(code)
+    ref_plan = make_plan(oc, list(arrival), lost, mode)
+    cols = min(64, w.N)
+    t0 = time.perf_counter()
+    pipeline.coded_matmul_ref(A, np.ascontiguousarray(B[:, :cols]), oc, ref_plan)
+    dt = time.perf_counter() - t0
+    more = int(cols * budget / max(dt, 1e-3))
+    cols = max(cols, min(w.N, more - more % 64))
+    t0 = time.perf_counter()
+    pipeline.coded_matmul_ref(A, np.ascontiguousarray(B[:, :cols]), oc, ref_plan)
+    dt = time.perf_counter() - t0
+    useful = 2.0 * w.M * w.K * cols
+    return {"value": useful / dt / 1e12, "unit": "TFLOP/s", "cores": blas_threads(),
+            "kind": "oracle",
+            "sample": f"float64 oracle coded pipeline (encode, {len(ref_plan.computed)} coded "
+                      f"products, peel) on all of A ({w.M}x{w.K}) and the first {cols} of "
+                      f"B's {w.N} columns, {dt:.1f} s"}
+
+
+# -------------------------------------------------------------------- batch --
+
+def run_batch(args):
+    import numpy as np
+    import torch
+
+    from paper_1904_11563_amd import autotune, bpx, inputs
+
+    tuned = autotune.load()
+    prec_name = args.prec or "bf16x3"
+    prec = bpx.PREC_NAMES[prec_name]
+    dev = torch.device("cuda:0")
+    codes = {4: build_code(bpx, inputs.CODE_642), 8: build_code(bpx, inputs.CODE_1282)}
+    shapes = inputs.batch_shapes(args.seed, 256)
+    plans, uplans, As, Bs, Cs, Cus = [], [], [], [], [], []
+    meta = []
+    for i, (M, K, N, k) in enumerate(shapes):
+        code = codes[k]
+        n = code.info()["n"]
+        arrival, _ = inputs.erasure_arrival(args.seed * 1000 + i, n, n - k)
+        plans.append(bpx.Plan(code, arrival, 0, bpx.MODE_STRAGGLER, M, K, N, prec))
+        uplans.append(bpx.Plan(bpx.Code.identity(k, 2), list(range(k)), 0,
+                               bpx.MODE_STRAGGLER, M, K, N, prec))
+        g = torch.Generator(device="cpu").manual_seed(args.seed * 1000 + i)
+        As.append(torch.randn(M, K, generator=g).to(dev))
+        Bs.append(torch.randn(K, N, generator=g).to(dev))
+        Cs.append(torch.empty(M, N, device=dev))
+        Cus.append(torch.empty(M, N, device=dev))
+        meta.append(plans[-1].info())
+    ws = torch.empty(bpx.group_workspace_bytes(plans), dtype=torch.uint8, device=dev)
+    uws = torch.empty(max(bpx.group_workspace_bytes(uplans), 256), dtype=torch.uint8, device=dev)
+    group = bpx.Group(plans, As, Bs, Cs, ws)
+    ugroup = bpx.Group(uplans, As, Bs, Cus, uws)
+
+    useful = sum(2.0 * M * K * N for (M, K, N, _) in shapes)
+
+    def capture(gr):
+        graph = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            gr.launch()          # warm (not captured)
+            torch.cuda.synchronize()
+            with torch.cuda.graph(graph, stream=s):
+                gr.launch()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        return graph
+
+    graph = capture(group)
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    value = useful / (ms * 1e-3) / 1e12
+
+    # phase durations (eager, events on the launch stream)
+    phase_ms = [timed(torch, lambda p=p: group.launch_phase(p), max(3, args.steps // 3))
+                for p in range(3)]
+    comp_flops = 0.0
+    for (M, K, N, k), inf in zip(shapes, meta):
+        comp_flops += 2.0 * inf["Mb"] * K * N * inf["n_computed"]
+    achieved = comp_flops / (phase_ms[1] * 1e-3) / 1e12
+
+    refs = {}
+    if not args.no_ref:
+        ugraph = capture(ugroup)
+        for _ in range(3):
+            ugraph.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ugraph.replay()
+        torch.cuda.synchronize()
+        refs["uncoded_own_tflops"] = useful / ((time.perf_counter() - t0) / args.steps) / 1e12
+        refs["uncoded_own_prec"] = prec_name
+        refs["frac_of_uncoded_own"] = value / refs["uncoded_own_tflops"]
+
+    # error: 8 sampled rows of every product against float64
+    num = den = 0.0
+    for i, (M, K, N, k) in enumerate(shapes):
+        rows = np.linspace(0, M - 1, 8).astype(int)
+        A = As[i][rows].double().cpu().numpy()
+        R = A @ Bs[i].double().cpu().numpy()
+        Cr = Cs[i][rows].double().cpu().numpy()
+        num += float(np.sum((Cr - R) ** 2))
+        den += float(np.sum(R ** 2))
+    rel_err = float(np.sqrt(num / den))
+
+    cfg = {"workload": "batch", "products": len(shapes),
+           "shapes": "M,K,N log-uniform in [256,4096], multiples of 128",
+           "codes": "(6,4,2) for k=4, (12,8,2) for k=8 (searched)", "mode": "arrival",
+           "mean_prefix_overhead": float(np.mean([m["n_computed"] * 1.0 /
+                                                  (2 * s[3]) for m, s in zip(meta, shapes)])),
+           "tile_table": "autotuned" if tuned else "default", "graph": "hipGraph replay",
+           "parallelism": "none (1 GPU)"}
+    out = header(args, value, ms, prec_name, cfg)
+    out.update({"rel_err": rel_err, "rel_err_sample": "8 rows x all columns of every product",
+                "times_ms": {"split_b": phase_ms[0], "grouped_gemm": phase_ms[1],
+                             "peel": phase_ms[2]},
+                "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[prec_name],
+                             "unit": "TFLOP/s", "frac": achieved / PEAK[prec_name],
+                             "traffic": load_traffic("batch", prec_name),
+                             "kernel": "gemm_bf16_grouped_kernel",
+                             "flops_per_launch": comp_flops, "launch_ms": phase_ms[1]}})
+    out.update(refs)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_batch(shapes, plans, codes, As, Bs, args)
+    return out
+
+
+def cpu_batch(shapes, plans, codes, As, Bs, args):
+    """The oracle on the smallest products of the batch until about
+    cpu-seconds of work."""
+    from oracle import pipeline
+    from oracle.peeling import make_plan
+    from paper_1904_11563_amd import inputs
+    order = sorted(range(len(shapes)), key=lambda i: shapes[i][0] * shapes[i][1] * shapes[i][2])
+    done, flops, t_total = 0, 0.0, 0.0
+    for i in order:
+        M, K, N, k = shapes[i]
+        code = codes[k]
+        n = code.info()["n"]
+        arrival, _ = inputs.erasure_arrival(args.seed * 1000 + i, n, n - k)
+        oc = oracle_code(code)
+        rp = make_plan(oc, list(arrival), 0, 1)
+        A = As[i].cpu().numpy()
+        B = Bs[i].cpu().numpy()
+        t0 = time.perf_counter()
+        pipeline.coded_matmul_ref(A, B, oc, rp)
+        t_total += time.perf_counter() - t0
+        flops += 2.0 * M * K * N
+        done += 1
+        if t_total > args.cpu_seconds:
+            break
+    return {"value": flops / t_total / 1e12, "unit": "TFLOP/s", "cores": blas_threads(),
+            "kind": "oracle",
+            "sample": f"float64 oracle coded pipeline on the {done} smallest of the 256 "
+                      f"products, {t_total:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+    import torch
+    torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        # a plain copy of known size: 1 GiB read, 1 GiB written per launch
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": x.numel() * 4, "launches": 3}), flush=True)
+        return
+    out = run_batch(args) if args.workload == "batch" else run_single(args)
     print(json.dumps(out), flush=True)
 
 

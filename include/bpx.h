@@ -268,6 +268,9 @@ bpx_status bpx_group_create(bpx_plan* const* plans, const float* const* A, const
                             float* const* C, int32_t count, void* ws, size_t ws_bytes,
                             bpx_group** out);
 bpx_status bpx_group_launch(bpx_group* group, bpx_stream stream);
+/* One phase of bpx_group_launch (0: B split, 1: GEMMs, 2: peel; -1: all),
+ * for timing the phases separately; the phases must run in order. */
+bpx_status bpx_group_launch_phase(bpx_group* group, int32_t phase, bpx_stream stream);
 void bpx_group_free(bpx_group* group);
 bpx_status bpx_coded_matmul_grouped(bpx_plan* const* plans, const float* const* A,
                                     const float* const* B, float* const* C, int32_t count,

@@ -14,6 +14,11 @@ import os
 
 import numpy as np
 
+# torch bundles its own HIP runtime (same soname as ROCm's).  Loading torch
+# first makes libbpx bind to that runtime, so the process has one HIP runtime
+# and device pointers and streams from torch are valid in the library.
+import torch  # noqa: F401,E402
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbpx.so")
 
@@ -40,7 +45,7 @@ EXPORTS = [
     "bpx_plan_workspace_layout",
     "bpx_plan_upload", "bpx_plan_free", "bpx_encode", "bpx_coded_gemm", "bpx_peel_decode",
     "bpx_coded_matmul", "bpx_coded_matmul_grouped", "bpx_group_workspace_bytes",
-    "bpx_group_create", "bpx_group_launch", "bpx_group_free",
+    "bpx_group_create", "bpx_group_launch", "bpx_group_launch_phase", "bpx_group_free",
     "bpx_tile_count", "bpx_set_tile_table", "bpx_force_tile", "bpx_last_error",
 ]
 
@@ -83,6 +88,7 @@ _sig = {
     "bpx_group_create": (C.c_int, [C.POINTER(_p), C.POINTER(_p), C.POINTER(_p), C.POINTER(_p),
                                    C.c_int32, _p, C.c_size_t, C.POINTER(_p)]),
     "bpx_group_launch": (C.c_int, [_p, _p]),
+    "bpx_group_launch_phase": (C.c_int, [_p, C.c_int32, _p]),
     "bpx_group_free": (None, [_p]),
     "bpx_tile_count": (C.c_int32, [C.c_int32]),
     "bpx_set_tile_table": (C.c_int, [_i32p, C.c_int32]),
@@ -365,6 +371,9 @@ class Group:
 
     def launch(self, stream=None):
         _check(_lib.bpx_group_launch(self._h, _stream(stream)))
+
+    def launch_phase(self, phase, stream=None):
+        _check(_lib.bpx_group_launch_phase(self._h, phase, _stream(stream)))
 
     def __del__(self):
         try:

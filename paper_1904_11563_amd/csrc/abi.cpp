@@ -402,17 +402,24 @@ bpx_status group_build(bpx_plan* const* plans, const float* const* A, const floa
   return BPX_OK;
 }
 
-bpx_status group_launch(bpx_group* g, hipStream_t stream) {
-  hipError_t e = launch_split_b_grouped(g->d_desc, g->d_bstart, g->count, g->total_b, stream);
-  if (e != hipSuccess) return hip_fail(e, "grouped split-B launch");
-  const int32_t split = g->prec == BPX_PREC_BF16X3 ? 3 : 1;
-  for (const GroupLaunch& L : g->launches) {
-    e = launch_gemm_bf16_grouped(g->d_desc, g->d_tiles + L.offset, L.n, L.tile, split, L.grid,
-                                 stream);
-    if (e != hipSuccess) return hip_fail(e, "grouped GEMM launch");
+bpx_status group_launch(bpx_group* g, int32_t phase, hipStream_t stream) {
+  hipError_t e;
+  if (phase < 0 || phase == 0) {
+    e = launch_split_b_grouped(g->d_desc, g->d_bstart, g->count, g->total_b, stream);
+    if (e != hipSuccess) return hip_fail(e, "grouped split-B launch");
   }
-  e = launch_peel_grouped(g->d_desc, g->d_pstart, g->count, g->total_p, g->max_slots, stream);
-  if (e != hipSuccess) return hip_fail(e, "grouped peel launch");
+  if (phase < 0 || phase == 1) {
+    const int32_t split = g->prec == BPX_PREC_BF16X3 ? 3 : 1;
+    for (const GroupLaunch& L : g->launches) {
+      e = launch_gemm_bf16_grouped(g->d_desc, g->d_tiles + L.offset, L.n, L.tile, split, L.grid,
+                                   stream);
+      if (e != hipSuccess) return hip_fail(e, "grouped GEMM launch");
+    }
+  }
+  if (phase < 0 || phase == 2) {
+    e = launch_peel_grouped(g->d_desc, g->d_pstart, g->count, g->total_p, g->max_slots, stream);
+    if (e != hipSuccess) return hip_fail(e, "grouped peel launch");
+  }
   return BPX_OK;
 }
 
@@ -642,12 +649,16 @@ bpx_status bpx_group_create(bpx_plan* const* plans, const float* const* A, const
   return BPX_OK;
 }
 
-bpx_status bpx_group_launch(bpx_group* group, bpx_stream stream) {
-  if (!group) return fail(BPX_E_INVALID, "null group");
+bpx_status bpx_group_launch_phase(bpx_group* group, int32_t phase, bpx_stream stream) {
+  if (!group || phase < -1 || phase > 2) return fail(BPX_E_INVALID, "null group or bad phase");
   int dev = 0;
   (void)hipGetDevice(&dev);
   if (dev != group->dev_id) return fail(BPX_E_INVALID, "group lives on another device");
-  return group_launch(group, reinterpret_cast<hipStream_t>(stream));
+  return group_launch(group, phase, reinterpret_cast<hipStream_t>(stream));
+}
+
+bpx_status bpx_group_launch(bpx_group* group, bpx_stream stream) {
+  return bpx_group_launch_phase(group, -1, stream);
 }
 
 void bpx_group_free(bpx_group* group) {
