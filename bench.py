@@ -231,6 +231,8 @@ def run_single(args):
                                                    refs["uncoded_torch_tflops"])
         refs["frac_of_uncoded_own"] = value / refs["uncoded_own_tflops"]
 
+    hbm = hbm_kernels(torch, bpx, plan, code, Ad, Cd, ws, w, info, args.steps)
+
     n_comp = info["n_computed"]
     gemm_flops = 2.0 * Mb * w.K * w.N * n_comp
     achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12
@@ -251,11 +253,43 @@ def run_single(args):
     out.update({"rel_err": rel_err, "rel_err_sample": f"{len(rows)} rows x all columns",
                 "times_ms": {"coded_gemm_call": gemm_ms, "peel": peel_ms,
                              "plan_host_us": plan_us, "code_build_s": code_s},
-                "roofline": roofline})
+                "roofline": roofline, "hbm": hbm})
     out.update(refs)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_single(A, B, code, arrival, lost, mode, w, args.cpu_seconds)
     return out
+
+
+def hbm_kernels(torch, bpx, plan, code, Ad, Cd, ws, w, info, steps):
+    """Achieved HBM GB/s of the two streaming kernels: the standalone encode
+    (bpx_encode) and the peel, each as algorithmic bytes / event time."""
+    sch = plan.schedule()
+    col_ptr, sym_ptr, sym_data = code.csr()
+    Mb, K, N, M = info["Mb"], w.K, w.N, w.M
+    rows = lambda s: max(0, min(Mb, M - s * Mb))
+    comp = sch["computed"].tolist()
+    enc_read = sum(rows(int(s)) * K * 4 for g in comp for s in sym_data[sym_ptr[g]:sym_ptr[g + 1]])
+    enc_write = len(comp) * Mb * K * 4
+    _, enc_bytes = plan.workspace_bytes()
+    out_enc = torch.empty(enc_bytes // 4, dtype=torch.float32, device=Ad.device)
+    bpx.encode(plan, Ad, out_enc)
+    enc_ms = timed(torch, lambda: bpx.encode(plan, Ad, out_enc), steps)
+    del out_enc
+    dest = dict(zip(comp, sch["dest"].tolist()))
+    used = set(sch["sub_data"].tolist())
+    rd = wr = 0
+    for s, g in enumerate(sch["releaser"].tolist()):
+        d = dest[g]
+        if d >= 0 or s in used:
+            rd += rows(s) * N * 4
+        if d >= 0:
+            wr += rows(s) * N * 4
+    peel_ms = timed(torch, lambda: bpx.peel_decode(plan, ws, Cd), steps)
+    res = {"peak_GBps": 8000.0}
+    for name, b, t in (("encode", enc_read + enc_write, enc_ms), ("peel", rd + wr, peel_ms)):
+        res[name] = {"bytes": b, "ms": t, "GBps": b / (t * 1e-3) / 1e9 if t > 0 else None,
+                     "frac": (b / (t * 1e-3) / 1e9) / 8000.0 if t > 0 else None}
+    return res
 
 
 def cpu_single(A, B, code, arrival, lost, mode, w, budget):

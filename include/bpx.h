@@ -284,6 +284,10 @@ bpx_status bpx_coded_matmul_grouped(bpx_plan* const* plans, const float* const* 
  * < 0 fall back to the default shape).  bpx_force_tile forces one shape for
  * every call (for the autotuner); -1 returns to the table. */
 int32_t bpx_tile_count(int32_t prec);
+/* Order in which the FP32 GEMM walks its output tiles: row panels (symbol x
+ * m-tile) in groups of group_m, each group finished column panel by column
+ * panel (1 = plain row-major order).  Affects speed and L2 reuse only. */
+bpx_status bpx_set_tile_order(int32_t group_m);
 bpx_status bpx_set_tile_table(const int32_t* table, int32_t n_entries);
 bpx_status bpx_force_tile(int32_t tile);
 

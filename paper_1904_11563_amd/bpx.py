@@ -46,7 +46,8 @@ EXPORTS = [
     "bpx_plan_upload", "bpx_plan_free", "bpx_encode", "bpx_coded_gemm", "bpx_peel_decode",
     "bpx_coded_matmul", "bpx_coded_matmul_grouped", "bpx_group_workspace_bytes",
     "bpx_group_create", "bpx_group_launch", "bpx_group_launch_phase", "bpx_group_free",
-    "bpx_tile_count", "bpx_set_tile_table", "bpx_force_tile", "bpx_last_error",
+    "bpx_tile_count", "bpx_set_tile_order", "bpx_set_tile_table", "bpx_force_tile",
+    "bpx_last_error",
 ]
 
 
@@ -93,6 +94,7 @@ _sig = {
     "bpx_tile_count": (C.c_int32, [C.c_int32]),
     "bpx_set_tile_table": (C.c_int, [_i32p, C.c_int32]),
     "bpx_force_tile": (C.c_int, [C.c_int32]),
+    "bpx_set_tile_order": (C.c_int, [C.c_int32]),
     "bpx_last_error": (C.c_char_p, []),
 }
 for _name, (_res, _args) in _sig.items():
@@ -394,6 +396,10 @@ def set_tile_table(table):
         return
     t = np.ascontiguousarray(table, dtype=np.int32)
     _check(_lib.bpx_set_tile_table(t.ctypes.data_as(_i32p), len(t)))
+
+
+def set_tile_order(group_m):
+    _check(_lib.bpx_set_tile_order(group_m))
 
 
 def force_tile(t):

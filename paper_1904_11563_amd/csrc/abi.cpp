@@ -14,6 +14,7 @@ namespace bpx {
 namespace {
 thread_local std::string g_error;
 int32_t g_force_tile = -1;
+int32_t g_group_m = 2;
 int32_t g_tile_table[8 * 8 * 8 * 5];
 bool g_tile_table_set = false;
 }  // namespace
@@ -146,6 +147,7 @@ bpx_status gemm_impl(bpx_plan* plan, const float* A, int64_t lda, const float* B
   p.ids = plan->d_gemm_ids;
   p.n_sym = (int32_t)plan->computed.size();
   p.prec = plan->prec;
+  p.group_m = g_group_m;
   // The GEMM kernels index A rows of a block and B rows of a K-slice with
   // 32-bit offsets.
   if ((plan->Mb + 256) * lda >= ((int64_t)1 << 30) || 64 * ldb + plan->N >= ((int64_t)1 << 30))
@@ -344,10 +346,10 @@ bpx_status group_build(bpx_plan* const* plans, const float* const* A, const floa
     bstart[i] = tb;
     tb += (int64_t)d.b_tn * d.b_tk;
     pstart[i] = tp;
-    if (pe.nsteps > 0) tp += (pl->Mb * pl->N + 255) / 256;
+    if (pe.nsteps > 0) tp += (pl->Mb * (pl->N / 4) + 127) / 128;
     w += bpx_plan::align256(pl->ws_bytes());
   }
-  if ((size_t)max_slots * 256 * 4 > 160 * 1024)
+  if ((size_t)max_slots * 128 * 16 > 160 * 1024)
     return fail(BPX_E_UNSUPPORTED, "peel needs more LDS than a workgroup has");
   // tile lists: longest K first (stable), one persistent launch per shape
   std::vector<GroupTile> tiles;
@@ -695,6 +697,12 @@ bpx_status bpx_set_tile_table(const int32_t* table, int32_t n_entries) {
   if (n_entries != need) return fail(BPX_E_INVALID, "tile table has the wrong size");
   std::memcpy(g_tile_table, table, sizeof(g_tile_table));
   g_tile_table_set = true;
+  return BPX_OK;
+}
+
+bpx_status bpx_set_tile_order(int32_t group_m) {
+  if (group_m < 1 || group_m > 64) return fail(BPX_E_INVALID, "group_m must be in [1, 64]");
+  g_group_m = group_m;
   return BPX_OK;
 }
 

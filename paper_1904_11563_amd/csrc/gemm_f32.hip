@@ -51,6 +51,26 @@ __device__ __forceinline__ int xcd_remap(int lin, int total) {
   return (lin & 7) * (total >> 3) + (lin >> 3);
 }
 
+// Tile index -> (row panel, column panel), row panels taken in groups of gm:
+// consecutive tiles walk down gm row panels before moving to the next column
+// panel, so the tiles one XCD runs together share A and B K-slices in L2.
+// Row panel = symbol * tiles_m + m-tile.
+__device__ __forceinline__ void tile_coords(int L, int rows, int cols, int gm, int* row,
+                                            int* col) {
+  if (gm <= 1) {
+    *row = L / cols;
+    *col = L - *row * cols;
+    return;
+  }
+  const int per_group = gm * cols;
+  const int g = L / per_group;
+  const int first = g * gm;
+  const int gsz = rows - first < gm ? rows - first : gm;
+  const int r = L - g * per_group;
+  *row = first + r % gsz;
+  *col = r / gsz;
+}
+
 template <int BM, int BN, int BK, int OCC>
 __global__ __launch_bounds__(kThreads, OCC) void coded_gemm_f32_kernel(GemmParams p) {
   using T = F32Tile<BM, BN, BK>;
@@ -66,11 +86,10 @@ __global__ __launch_bounds__(kThreads, OCC) void coded_gemm_f32_kernel(GemmParam
 
   const int total = gridDim.x;
   const int lin = xcd_remap(blockIdx.x, total);
-  const int per_sym = p.tiles_m * p.tiles_n;
-  const int si = lin / per_sym;
-  const int rem = lin - si * per_sym;
-  const int mt = rem / p.tiles_n;
-  const int nt = rem - mt * p.tiles_n;
+  int rp, nt;
+  tile_coords(lin, p.n_sym * p.tiles_m, p.tiles_n, p.group_m, &rp, &nt);
+  const int si = rp / p.tiles_m;
+  const int mt = rp - si * p.tiles_m;
   const int m0 = mt * BM, n0 = nt * BN;
 
   const int id_off = p.syms[4 * si + 0];

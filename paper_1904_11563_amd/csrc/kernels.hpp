@@ -28,6 +28,7 @@ struct GemmParams {
   int32_t n_sym;
   int32_t tiles_m, tiles_n;
   int32_t prec;  // bpx_prec
+  int32_t group_m;  // tile order: row panels per group (1 = row-major order)
   // BF16 / BF16x3: B split into transposed bf16 planes (N x kp, k contiguous)
   const unsigned short* bt_hi;
   const unsigned short* bt_lo;
