@@ -236,7 +236,12 @@ def run_single(args):
     n_comp = info["n_computed"]
     gemm_flops = 2.0 * Mb * w.K * w.N * n_comp
     achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12
-    kernel = {"f32": "coded_gemm_f32_kernel", "bf16": "split_b + coded_gemm_bf16_kernel",
+    if Mb % 256 == 0 and w.N % 256 == 0 and w.K % 32 == 0 and w.M % Mb == 0:
+        f32_kernel = ("coded_gemm_f32_wide_kernel<4,2> (full rounds of 256x256 tiles) + "
+                      "coded_gemm_f32_kernel<64,128,32,2> (last round as sub-tiles), one call")
+    else:
+        f32_kernel = "coded_gemm_f32_kernel<64,128,32,2>"
+    kernel = {"f32": f32_kernel, "bf16": "split_b + coded_gemm_bf16_kernel",
               "bf16x3": "split_b + coded_gemm_bf16_kernel",
               "fp8": "quant_b + quant_a + coded_gemm_fp8_kernel",
               "fp8x2": "quant_b + quant_a + coded_gemm_fp8_kernel"}[prec_name]

@@ -282,7 +282,13 @@ bpx_status bpx_coded_matmul_grouped(bpx_plan* const* plans, const float* const* 
  * x = Mb, N, K) and the precision to a tile-shape index, indexed
  * ((prec*8 + bMb)*8 + bN)*8 + bK (8*8*8*5 entries; NULL clears it; entries
  * < 0 fall back to the default shape).  bpx_force_tile forces one shape for
- * every call (for the autotuner); -1 returns to the table. */
+ * every call (for the autotuner); -1 returns to the table.
+ * FP32 shapes 0-3 are 128x128, 64x128, 128x256 and 256x128; 4-6 are 256x256
+ * with 2x2, 2x4 and 4x2 waves (the default), used when Mb and N are
+ * multiples of 256, K of 32 and every data block is full, otherwise the call
+ * takes shape 1; a last round of 256x256 tiles under 90% of the CUs runs as
+ * 64x128 sub-tiles.  Every FP32 shape sums in the same order, so the shape
+ * never changes a result. */
 int32_t bpx_tile_count(int32_t prec);
 /* Order in which the FP32 GEMM walks its output tiles: row panels (symbol x
  * m-tile) in groups of group_m, each group finished column panel by column

@@ -59,12 +59,13 @@ int32_t choose_tile(int32_t prec, int64_t Mb, int64_t N, int64_t K) {
     if (t >= 0 && t < tile_count_for(prec)) return t;
   }
   if (prec == BPX_PREC_BF16 || prec == BPX_PREC_BF16X3) return 1;  // 64x128, no spills
-  // default: 64x128 (three workgroups per CU) measured fastest for the FP32
-  // products on 8192x8192x4096 and for small blocks
+  // FP32 default: the 256 x 256 tile with 4 x 2 waves (measured fastest on
+  // 8192x8192x4096); its launcher takes the 64 x 128 tile for shapes that
+  // are not multiples of 256 and for grids under one round.
   (void)Mb;
   (void)N;
   (void)K;
-  return 1;
+  return 6;
 }
 
 bpx_status upload(bpx_plan* plan) {

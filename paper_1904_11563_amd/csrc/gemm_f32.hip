@@ -84,13 +84,23 @@ __global__ __launch_bounds__(kThreads, OCC) void coded_gemm_f32_kernel(GemmParam
   const int wm = wave >> 1, wn = wave & 1;
   const int q = lane >> 4, c16 = lane & 15;
 
-  const int total = gridDim.x;
-  const int lin = xcd_remap(blockIdx.x, total);
-  int rp, nt;
-  tile_coords(lin, p.n_sym * p.tiles_m, p.tiles_n, p.group_m, &rp, &nt);
-  const int si = rp / p.tiles_m;
-  const int mt = rp - si * p.tiles_m;
-  const int m0 = mt * BM, n0 = nt * BN;
+  int rp, nt, si, m0, n0;
+  if (p.wide_rem) {
+    // sub-tile of a 256 x 256 tile left over from the wide launch
+    constexpr int SN = 256 / BN, PER = (256 / BM) * SN;
+    const int sub = blockIdx.x % PER;
+    tile_coords(p.wide_lin0 + (int)blockIdx.x / PER, p.n_sym * p.tiles_m, p.tiles_n, p.group_m,
+                &rp, &nt);
+    si = rp / p.tiles_m;
+    m0 = (rp - si * p.tiles_m) * 256 + (sub / SN) * BM;
+    n0 = nt * 256 + (sub % SN) * BN;
+  } else {
+    const int lin = xcd_remap(blockIdx.x, gridDim.x);
+    tile_coords(lin, p.n_sym * p.tiles_m, p.tiles_n, p.group_m, &rp, &nt);
+    si = rp / p.tiles_m;
+    m0 = (rp - si * p.tiles_m) * BM;
+    n0 = nt * BN;
+  }
 
   const int id_off = p.syms[4 * si + 0];
   const int deg = p.syms[4 * si + 1];
@@ -329,33 +339,273 @@ __global__ __launch_bounds__(kThreads, OCC) void coded_gemm_f32_kernel(GemmParam
   }
 }
 
+// ------------------------------------------------------------ wide tile --
+// 256 x 256 x 32 tile for shapes whose every tile is interior (Mb and N
+// multiples of 256, K of 32, every data block full).  WM x WN waves each own
+// a (256/WM) x (256/WN) wave tile whose accumulators live in the AGPR half
+// of the register file, so that a K-slice is many MFMAs per wave between
+// barriers.  Global loads are raw buffer loads: the per-thread offset is one
+// 32-bit register each for A and B, the member block and the slice are in
+// the (scalar) buffer resource and the row group in the scalar offset.  The
+// loads and sums of members past deg are skipped by uniform branches (an
+// empty buffer resource would return zeros without touching memory, but its
+// loads still cost address-unit cycles: measured 7 % slower).
+namespace wide {
+constexpr int BM = 256, BN = 256, BK = 32;
+constexpr int LDA_S = BK + 4, LDB_S = BN + 4;
+constexpr int A_SIZE = BM * LDA_S, B_SIZE = BK * LDB_S;
+constexpr int kRsrcWord3 = 0x00020000;  // gfx9 raw buffer, 32-bit elements
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const float* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, bytes, kRsrcWord3);
+}
+__device__ __forceinline__ v4f bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(v4f,
+                            __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+}
+}  // namespace wide
+
+template <int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN, 1) void coded_gemm_f32_wide_kernel(GemmParams p) {
+  using namespace wide;
+  constexpr int NT = 64 * WM * WN;               // threads
+  constexpr int TM = BM / WM, TN = BN / WN;      // wave tile
+  constexpr int FM = TM / 16, FN = TN / 16;      // 16 x 16 subtiles per wave
+  constexpr int U = (BM / 2) * BK / 4 / NT;      // float4 per thread per half slice
+  constexpr int RA = NT / 8, RB = NT / 64;       // row step of a thread's A / B loads
+  static_assert(U >= 1 && FN % 4 == 0 && (BK / 2) * BN / 4 / NT == U, "tile split");
+  __shared__ __attribute__((aligned(16))) float lds[2 * (A_SIZE + B_SIZE)];
+  float* As0 = lds;
+  float* Bs0 = lds + 2 * A_SIZE;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int q = lane >> 4, c16 = lane & 15;
+
+  const int lin = xcd_remap(blockIdx.x, gridDim.x);
+  int rp, nt;
+  tile_coords(lin, p.n_sym * p.tiles_m, p.tiles_n, p.group_m, &rp, &nt);
+  const int si = rp / p.tiles_m;
+  const int mt = rp - si * p.tiles_m;
+  const int m0 = mt * BM, n0 = nt * BN;
+
+  const int id_off = p.syms[4 * si + 0];
+  const int deg = p.syms[4 * si + 1];
+  const int dest = p.syms[4 * si + 2];
+  const int32_t* ids = p.ids + id_off;
+  const int64_t lda = p.lda, ldb = p.ldb;
+
+  // Half h of a slice: A rows 128 h + ar + RA u, k ak .. ak+3; B k-rows
+  // 16 h + br + RB u, columns bc .. bc+3 (u < U).
+  const int ar = tid >> 3, ak = (tid & 7) * 4;
+  const int br = tid >> 6, bc = (tid & 63) * 4;
+  const uint32_t a_off = (uint32_t)(((int64_t)(m0 + ar) * lda + ak) * 4);
+  const uint32_t b_off = (uint32_t)(((int64_t)br * ldb + bc) * 4);
+  const uint32_t a_row4 = (uint32_t)(lda * 4), b_row4 = (uint32_t)(ldb * 4);
+  const int64_t blk = p.Mb * lda;  // floats per data block
+  const int id0 = ids[0];
+  const int id1 = deg > 1 ? ids[1] : 0;
+  const int id2 = deg > 2 ? ids[2] : 0;
+  const int id3 = deg > 3 ? ids[3] : 0;
+  static_assert(kPre == 4, "member ids are held in four scalars");
+
+  v4f pre[kPre][U];
+  v4f bre[U];
+  auto load_half = [&](int h, int k0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int m = 0; m < kPre; ++m) {
+      const int id = m == 0 ? id0 : m == 1 ? id1 : m == 2 ? id2 : id3;
+      if (m < deg) {
+        const auto r = rsrc(p.A + id * blk + k0, -1);
+#pragma unroll
+        for (int u = 0; u < U; ++u) pre[m][u] = bload(r, a_off, (128 * h + RA * u) * a_row4);
+      }
+    }
+    const auto rb = rsrc(p.B + (int64_t)k0 * ldb + n0, -1);
+#pragma unroll
+    for (int u = 0; u < U; ++u) bre[u] = bload(rb, b_off, (16 * h + RB * u) * b_row4);
+  };
+  auto store_half = [&](int h, int buf, int k0) __attribute__((always_inline)) {
+    float* As = As0 + buf * A_SIZE + ar * LDA_S + ak;
+    float* Bs = Bs0 + buf * B_SIZE + br * LDB_S + bc;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      v4f sum = pre[0][u];
+#pragma unroll
+      for (int m = 1; m < kPre; ++m)
+        if (m < deg) sum += pre[m][u];
+      if (deg > kPre) {  // members beyond the prefetch depth
+        for (int m = kPre; m < deg; ++m)
+          sum += bload(rsrc(p.A + ids[m] * blk + k0, -1), a_off, (128 * h + RA * u) * a_row4);
+      }
+      *reinterpret_cast<v4f*>(As + (128 * h + RA * u) * LDA_S) = sum;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      *reinterpret_cast<v4f*>(Bs + (16 * h + RB * u) * LDB_S) = bre[u];
+  };
+
+  v4f acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  auto compute_chunk = [&](const float* As, const float* Bs, int kk) __attribute__((always_inline)) {
+    v4f a[FM];
+    v4f b[FN / 4][4];
+    const float* Aw = As + (wm * TM + c16) * LDA_S + kk + 4 * q;
+    const float* Bw = Bs + (kk + 4 * q) * LDB_S + wn * TN + 4 * c16;
+#pragma unroll
+    for (int i = 0; i < FM; ++i) a[i] = *reinterpret_cast<const v4f*>(Aw + i * 16 * LDA_S);
+#pragma unroll
+    for (int jg = 0; jg < FN / 4; ++jg)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        b[jg][t] = *reinterpret_cast<const v4f*>(Bw + t * LDB_S + jg * 64);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][t], b[j / 4][t][j % 4],
+                                                           acc[i][j], 0, 0, 0);
+  };
+
+  const int nk = (int)(p.K / BK);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    load_half(h, 0);
+    store_half(h, 0, 0);
+  }
+  __syncthreads();
+  for (int kt = 0; kt + 1 < nk; ++kt) {
+    const int buf = kt & 1;
+    const int kn = (kt + 1) * BK;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      load_half(h, kn);
+      compute_chunk(As0 + buf * A_SIZE, Bs0 + buf * B_SIZE, h * 16);
+      store_half(h, buf ^ 1, kn);
+    }
+    __syncthreads();
+  }
+  {
+    const int buf = (nk - 1) & 1;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) compute_chunk(As0 + buf * A_SIZE, Bs0 + buf * B_SIZE, h * 16);
+  }
+
+  float* out;
+  int64_t ldo;
+  if (dest >= 0) {
+    out = p.Y + (int64_t)dest * p.Mb * p.N;
+    ldo = p.N;
+  } else {
+    out = p.C + (int64_t)(-1 - dest) * p.Mb * p.ldc;
+    ldo = p.ldc;
+  }
+#pragma unroll
+  for (int jg = 0; jg < FN / 4; ++jg) {
+    const int64_t col = n0 + wn * TN + jg * 64 + 4 * c16;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = m0 + wm * TM + i * 16 + 4 * q + r;
+        const v4f v = {acc[i][4 * jg + 0][r], acc[i][4 * jg + 1][r], acc[i][4 * jg + 2][r],
+                       acc[i][4 * jg + 3][r]};
+        *reinterpret_cast<v4f*>(out + row * ldo + col) = v;
+      }
+  }
+}
+
 struct TileEntry {
   TileShape shape;
   void (*kernel)(GemmParams);
+  unsigned threads;
 };
 
 const TileEntry kTiles[] = {
-    {{128, 128, 32}, coded_gemm_f32_kernel<128, 128, 32, 2>},
-    {{64, 128, 32}, coded_gemm_f32_kernel<64, 128, 32, 2>},
-    {{128, 256, 32}, coded_gemm_f32_kernel<128, 256, 32, 1>},
-    {{256, 128, 32}, coded_gemm_f32_kernel<256, 128, 32, 1>},
-    {{256, 256, 32}, coded_gemm_f32_kernel<256, 256, 32, 1>},
+    {{128, 128, 32}, coded_gemm_f32_kernel<128, 128, 32, 2>, kThreads},
+    {{64, 128, 32}, coded_gemm_f32_kernel<64, 128, 32, 2>, kThreads},
+    {{128, 256, 32}, coded_gemm_f32_kernel<128, 256, 32, 1>, kThreads},
+    {{256, 128, 32}, coded_gemm_f32_kernel<256, 128, 32, 1>, kThreads},
+    // interior shapes only:
+    {{256, 256, 32}, coded_gemm_f32_wide_kernel<2, 2>, 256},
+    {{256, 256, 32}, coded_gemm_f32_wide_kernel<2, 4>, 512},
+    {{256, 256, 32}, coded_gemm_f32_wide_kernel<4, 2>, 512},
 };
+
+constexpr int32_t kWideTile = 4;
 
 }  // namespace
 
 int32_t gemm_tile_count() { return (int32_t)(sizeof(kTiles) / sizeof(kTiles[0])); }
 TileShape gemm_tile_shape(int32_t t) { return kTiles[t].shape; }
 
+static int num_cus() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n <= 0)
+      n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
+
 hipError_t launch_coded_gemm(const GemmParams& p0, int32_t tile, hipStream_t stream) {
   GemmParams p = p0;
+  p.wide_rem = 0;
+  p.wide_lin0 = 0;
+  if (tile >= kWideTile) {
+    // The wide tile has no edge path: shapes with a partial tile, a partial
+    // data block or a ragged last K-slice take the 64 x 128 tile.
+    const bool fits = p.Mb % 256 == 0 && p.N % 256 == 0 && p.K % 32 == 0 &&
+                      p.M % p.Mb == 0 && p.ldc % 4 == 0;
+    const int64_t T = fits ? (int64_t)p.n_sym * (p.Mb / 256) * (p.N / 256) : 0;
+    const int64_t S = num_cus();  // one 256 x 256 workgroup per CU
+    // Full rounds of 256 x 256 tiles run wide; a last round under 90 % full
+    // runs as 64 x 128 sub-tiles (eight per tile, several per CU), which
+    // keeps every CU busy to the end.  Both kernels sum in the same order,
+    // so the split does not change results.
+    const int64_t rem = T % S;
+    const int64_t wide_tiles = rem * 10 < S * 9 ? T - rem : T;
+    if (T == 0 || T > 0x7fffffff / 8) {
+      tile = 1;
+    } else {
+      const TileEntry& e = kTiles[tile];
+      p.tiles_m = (int32_t)(p.Mb / 256);
+      p.tiles_n = (int32_t)(p.N / 256);
+      if (wide_tiles > 0) {
+        hipLaunchKernelGGL(e.kernel, dim3((unsigned)wide_tiles), dim3(e.threads), 0, stream, p);
+        hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
+      }
+      if (wide_tiles == T) return hipSuccess;
+      const TileEntry& s = kTiles[1];
+      p.wide_rem = 1;
+      p.wide_lin0 = (int32_t)wide_tiles;
+      const int64_t per = (256 / s.shape.bm) * (256 / s.shape.bn);
+      hipLaunchKernelGGL(s.kernel, dim3((unsigned)((T - wide_tiles) * per)), dim3(s.threads), 0,
+                         stream, p);
+      return hipGetLastError();
+    }
+  }
   const TileEntry& e = kTiles[tile];
   p.tiles_m = (int32_t)((p.Mb + e.shape.bm - 1) / e.shape.bm);
   p.tiles_n = (int32_t)((p.N + e.shape.bn - 1) / e.shape.bn);
   const int64_t blocks = (int64_t)p.n_sym * p.tiles_m * p.tiles_n;
   if (blocks == 0) return hipSuccess;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(e.kernel, dim3((unsigned)blocks), dim3(kThreads), 0, stream, p);
+  hipLaunchKernelGGL(e.kernel, dim3((unsigned)blocks), dim3(e.threads), 0, stream, p);
   return hipGetLastError();
 }
 

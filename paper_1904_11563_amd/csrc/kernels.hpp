@@ -29,6 +29,11 @@ struct GemmParams {
   int32_t tiles_m, tiles_n;
   int32_t prec;  // bpx_prec
   int32_t group_m;  // tile order: row panels per group (1 = row-major order)
+  // Remainder mode of the 256 x 256 tiling (FP32 only): when wide_rem is set,
+  // tiles_m / tiles_n count 256 x 256 tiles and block b computes sub-tile
+  // b % per of 256 x 256 tile wide_lin0 + b / per (per = sub-tiles per tile).
+  int32_t wide_rem;
+  int32_t wide_lin0;
   // BF16 / BF16x3: B split into transposed bf16 planes (N x kp, k contiguous)
   const unsigned short* bt_hi;
   const unsigned short* bt_lo;

@@ -296,6 +296,40 @@ def test_fp32_scale_full_size_sampled():
     assert np.isfinite(C).all()
 
 
+def test_wide_tile_exact_and_identical_to_small_tile():
+    """The 256 x 256 FP32 tiles (three wave layouts) on a shape that fills
+    more than one round of the CUs, so that the last round runs as 64 x 128
+    sub-tiles of the wide tiling: integer operands decode to A.B exactly, and
+    float operands give bit-identical results to the 64 x 128 tile (every
+    FP32 tile shape sums in the same order)."""
+    code = code642()
+    M, K, N = 2048, 96, 6144           # Mb = 256; 12 symbols x 24 column tiles
+    arrival = list(range(6))
+    plan = bpx.Plan(code, arrival, 0, bpx.MODE_FULL, M, K, N)
+    assert plan.info()["Mb"] == 256 and plan.info()["n_computed"] == 12
+    A = inputs.integers(7, inputs.TAG_A, (M, K))
+    B = inputs.integers(7, inputs.TAG_B, (K, N))
+    R = A.astype(np.float64) @ B.astype(np.float64)
+    Af = inputs.normal(7, inputs.TAG_A, (M, K))
+    Bf = inputs.normal(7, inputs.TAG_B, (K, N))
+    try:
+        for tile in (4, 5, 6):
+            _say("wide tile", tile, "integer")
+            bpx.force_tile(tile)
+            C = run(plan, A, B)
+            assert np.array_equal(C.astype(np.float64), R), tile
+        bpx.force_tile(1)
+        C1 = run(plan, Af, Bf)
+        for tile in (4, 5, 6):
+            _say("wide tile", tile, "float vs 64x128")
+            bpx.force_tile(tile)
+            Cw = run(plan, Af, Bf)
+            assert np.array_equal(Cw, C1), tile
+    finally:
+        bpx.force_tile(-1)
+    assert relf(C1, Af.astype(np.float64) @ Bf.astype(np.float64)) <= TOL_F32
+
+
 # ------------------------------------------------------------ BF16 paths --
 
 TOL_BF16X3 = 1e-5
