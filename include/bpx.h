@@ -288,7 +288,10 @@ bpx_status bpx_coded_matmul_grouped(bpx_plan* const* plans, const float* const* 
  * multiples of 256, K of 32 and every data block is full, otherwise the call
  * takes shape 1; a last round of 256x256 tiles under 90% of the CUs runs as
  * 64x128 sub-tiles.  Every FP32 shape sums in the same order, so the shape
- * never changes a result. */
+ * never changes a result.  FP8 / FP8x2: shape 0 is one 128x128 tile grid per
+ * symbol, shape 1 (the default) one grid of 128x256 tiles over all symbols'
+ * codes, used when N rounded up to 128 is a multiple of 256, otherwise
+ * shape 0. */
 int32_t bpx_tile_count(int32_t prec);
 /* Order in which the FP32 GEMM walks its output tiles: row panels (symbol x
  * m-tile) in groups of group_m, each group finished column panel by column

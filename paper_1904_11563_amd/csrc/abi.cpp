@@ -46,8 +46,9 @@ int32_t log2_bucket(int64_t x) {
 }
 
 int32_t tile_count_for(int32_t prec) {
-  return (prec == BPX_PREC_BF16 || prec == BPX_PREC_BF16X3) ? bf16_tile_count()
-                                                              : gemm_tile_count();
+  if (prec == BPX_PREC_BF16 || prec == BPX_PREC_BF16X3) return bf16_tile_count();
+  if (prec == BPX_PREC_FP8 || prec == BPX_PREC_FP8X2) return fp8_tile_count();
+  return gemm_tile_count();
 }
 
 int32_t choose_tile(int32_t prec, int64_t Mb, int64_t N, int64_t K) {
@@ -59,6 +60,7 @@ int32_t choose_tile(int32_t prec, int64_t Mb, int64_t N, int64_t K) {
     if (t >= 0 && t < tile_count_for(prec)) return t;
   }
   if (prec == BPX_PREC_BF16 || prec == BPX_PREC_BF16X3) return 1;  // 64x128, no spills
+  if (prec == BPX_PREC_FP8 || prec == BPX_PREC_FP8X2) return 1;    // wide tiling
   // FP32 default: the 256 x 256 tile with 4 x 2 waves (measured fastest on
   // 8192x8192x4096); its launcher takes the 64 x 128 tile for shapes that
   // are not multiples of 256 and for grids under one round.
@@ -186,7 +188,7 @@ bpx_status gemm_impl(bpx_plan* plan, const float* A, int64_t lda, const float* B
       return fail(BPX_E_UNSUPPORTED, "FP8 grid too large");
     e = launch_quant_b(f, stream);
     if (e == hipSuccess) e = launch_quant_a(f, stream);
-    if (e == hipSuccess) e = launch_coded_gemm_fp8(f, stream);
+    if (e == hipSuccess) e = launch_coded_gemm_fp8(f, tile, stream);
   } else if (plan->prec == BPX_PREC_BF16 || plan->prec == BPX_PREC_BF16X3) {
     char* planes = static_cast<char*>(ws) + bpx_plan::align256(plan->y_bytes());
     void* hi = planes;
@@ -684,10 +686,7 @@ bpx_status bpx_coded_matmul_grouped(bpx_plan* const* plans, const float* const* 
   return BPX_OK;
 }
 
-int32_t bpx_tile_count(int32_t prec) {
-  return (prec == BPX_PREC_BF16 || prec == BPX_PREC_BF16X3) ? bf16_tile_count()
-                                                              : gemm_tile_count();
-}
+int32_t bpx_tile_count(int32_t prec) { return tile_count_for(prec); }
 
 bpx_status bpx_set_tile_table(const int32_t* table, int32_t n_entries) {
   const int32_t need = (int32_t)(sizeof(g_tile_table) / sizeof(g_tile_table[0]));

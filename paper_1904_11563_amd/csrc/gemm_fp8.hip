@@ -296,6 +296,182 @@ __global__ __launch_bounds__(kThreads, 1) void coded_gemm_fp8_kernel(Fp8Params p
     }
 }
 
+// ----------------------------------------------------------- wide tile --
+// The coded blocks' codes are one matrix of R = n_sym * Mbp rows (Mbp a
+// multiple of 128), so the products of all symbols form one R x Np x Kp
+// GEMM whose 128-row blocks each belong to one symbol.  Tiles of BM x 256
+// (BM = 128: a 256-row tile with FP32 accumulators does not fit the
+// registers), 8 waves of (BM / WM) x (256 / WN), each wave inside one 128 x 128
+// scale block, so the per-chunk scale sA sB is one number per wave.  The
+// residual plane's factor 1/16 is applied by the MFMA's own E8M0 scale
+// (2^-4), so both planes accumulate into the same chunk product before the
+// FP32 scale is applied.  Global loads are raw buffer loads (scalar
+// resource per plane and chunk, one 32-bit per-thread offset).
+namespace wide8 {
+constexpr int BN = 256;
+constexpr int NT = 512;
+constexpr int kRsrcWord3 = 0x00020000;  // gfx9 raw buffer, 32-bit elements
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const unsigned char* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<unsigned char*>(base), (short)0, -1,
+                                           kRsrcWord3);
+}
+__device__ __forceinline__ v4u bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+}
+}  // namespace wide8
+
+template <int BM, int WM, int WN, int X2>
+__global__ __launch_bounds__(wide8::NT, 1) void coded_gemm_fp8_wide_kernel(Fp8Params p) {
+  using namespace wide8;
+  constexpr int TM = BM / WM, TN = BN / WN;   // wave tile
+  constexpr int FM = TM / 16, FN = TN / 16;
+  constexpr int NA = X2 ? 2 : 1;              // A planes
+  constexpr int PA = BM * 8 / NT;             // 16-byte pieces per thread per A plane
+  constexpr int PB = BN * 8 / NT;             // and for B
+  constexpr int STAGE = (NA * BM + BN) * RS;  // bytes per LDS stage
+  static_assert(TM <= 128 && TN <= 128 && FN % 4 == 0 && PA >= 1, "wave tile");
+  __shared__ __attribute__((aligned(16))) unsigned char lds[2 * STAGE];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int q = lane >> 4, c16 = lane & 15;
+
+  const int lin = xcd_remap(blockIdx.x, gridDim.x);
+  const int mt = lin / p.tiles_n;
+  const int nt = lin - mt * p.tiles_n;
+  const int64_t m0 = (int64_t)mt * BM, n0 = (int64_t)nt * BN;
+  const int64_t Kp = p.Kp;
+  const int64_t plane = (int64_t)p.n_sym * p.Mbp * Kp;  // bytes per A plane
+
+  // piece f = tid + NT u: row f / 8, bytes (f % 8) * 16 of the 128-byte chunk row
+  const uint32_t voff = (uint32_t)((tid >> 3) * Kp + (tid & 7) * 16);
+  const uint32_t ustep = (uint32_t)((NT / 8) * Kp);
+  v4u ra[NA][PA], rb[PB];
+  auto load = [&](int c) __attribute__((always_inline)) {
+    const int64_t kc = (int64_t)c * CK;
+    const auto r0 = rsrc(p.aq + m0 * Kp + kc);
+#pragma unroll
+    for (int u = 0; u < PA; ++u) ra[0][u] = bload(r0, voff, u * ustep);
+    if (X2) {
+      const auto r1 = rsrc(p.aq2 + m0 * Kp + kc);
+#pragma unroll
+      for (int u = 0; u < PA; ++u) ra[NA - 1][u] = bload(r1, voff, u * ustep);
+    }
+    const auto r2 = rsrc(p.bq + n0 * Kp + kc);
+#pragma unroll
+    for (int u = 0; u < PB; ++u) rb[u] = bload(r2, voff, u * ustep);
+  };
+  const int srow = tid >> 3, sbyte = (tid & 7) * 16;
+  auto store = [&](int buf) __attribute__((always_inline)) {
+    unsigned char* st = lds + buf * STAGE + srow * RS + sbyte;
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+      for (int u = 0; u < PA; ++u)
+        *reinterpret_cast<v4u*>(st + (a * BM + u * (NT / 8)) * RS) = ra[a][u];
+#pragma unroll
+    for (int u = 0; u < PB; ++u)
+      *reinterpret_cast<v4u*>(st + (NA * BM + u * (NT / 8)) * RS) = rb[u];
+  };
+
+  v4f acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  const int64_t kc128 = Kp / 128;
+  const float* sa = p.sa + ((m0 + wm * TM) / 128) * kc128;
+  const float* sbp = p.sb + (n0 + wn * TN) / 128;
+  const int64_t np128 = p.Np / 128;
+
+  auto compute = [&](int buf, int c) __attribute__((always_inline)) {
+    const unsigned char* st = lds + buf * STAGE;
+    const float s = sa[c] * sbp[(int64_t)c * np128];
+    v8i a[NA][FM];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int pl = 0; pl < NA; ++pl)
+        a[pl][i] = *reinterpret_cast<const v8i*>(st + (pl * BM + wm * TM + i * 16 + c16) * RS +
+                                                 32 * q);
+#pragma unroll
+    for (int jg = 0; jg < FN / 4; ++jg) {
+      v8i b[4];
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int n = wn * TN + jg * 64 + 4 * c16 + jj;  // interleaved output columns
+        b[jj] = *reinterpret_cast<const v8i*>(st + (NA * BM + n) * RS + 32 * q);
+      }
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          v4f part = {0.f, 0.f, 0.f, 0.f};
+          if (X2)  // residual plane, E8M0 scale 2^-4
+            part = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[1][i], b[jj], part, 0, 0,
+                                                                     0, 123, 0, 127);
+          part = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[0][i], b[jj], part, 0, 0, 0,
+                                                                   127, 0, 127);
+          acc[i][jg * 4 + jj] += s * part;
+        }
+    }
+  };
+
+  const int nc = (int)(Kp / CK);
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int c = 0; c + 1 < nc; ++c) {
+    load(c + 1);
+    compute(c & 1, c);
+    store((c + 1) & 1);
+    __syncthreads();
+  }
+  compute((nc - 1) & 1, nc - 1);
+
+  // The wave's rows lie in one 128-row block, hence in one symbol.
+  const int64_t wrow = m0 + wm * TM;
+  const int si = (int)(wrow / p.Mbp);
+  const int64_t lrow0 = wrow - (int64_t)si * p.Mbp;
+  const int dest = p.syms[4 * si + 2];
+  float* out;
+  int64_t ldo, rows;
+  if (dest >= 0) {
+    out = p.Y + (int64_t)dest * p.Mb * p.N;
+    ldo = p.N;
+    rows = p.Mb;
+  } else {
+    const int64_t sblk = -1 - dest;
+    out = p.C + sblk * p.Mb * p.ldc;
+    ldo = p.ldc;
+    rows = p.M - sblk * p.Mb < p.Mb ? p.M - sblk * p.Mb : p.Mb;
+  }
+  const bool vec_ok = (ldo & 3) == 0;
+#pragma unroll
+  for (int jg = 0; jg < FN / 4; ++jg) {
+    const int64_t col = n0 + wn * TN + jg * 64 + 4 * c16;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = lrow0 + i * 16 + 4 * q + r;
+        if (row >= rows) continue;
+        float* dst = out + row * ldo + col;
+        const v4f v = {acc[i][4 * jg + 0][r], acc[i][4 * jg + 1][r], acc[i][4 * jg + 2][r],
+                       acc[i][4 * jg + 3][r]};
+        if (col + 3 < p.N && vec_ok) {
+          *reinterpret_cast<v4f*>(dst) = v;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (col + e < p.N) dst[e] = v[e];
+        }
+      }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_quant_a(const Fp8Params& p, hipStream_t stream) {
@@ -311,8 +487,29 @@ hipError_t launch_quant_b(const Fp8Params& p, hipStream_t stream) {
   return hipGetLastError();
 }
 
-hipError_t launch_coded_gemm_fp8(const Fp8Params& p0, hipStream_t stream) {
+int32_t fp8_tile_count() { return 2; }
+
+// tile 0: 128 x 128 per symbol; tile 1: 128 x 256 tiles over all symbols'
+// codes (used when Np is a multiple of 256, otherwise tile 0).
+hipError_t launch_coded_gemm_fp8(const Fp8Params& p0, int32_t tile, hipStream_t stream) {
   Fp8Params p = p0;
+  if (p.n_sym == 0) return hipSuccess;
+  const int64_t R = (int64_t)p.n_sym * p.Mbp;
+  const int64_t bm = 128;
+  if (tile == 1 && p.Np % 256 == 0 && R % bm == 0 && R * p.Kp < (int64_t)1 << 32 &&
+      p.Np * p.Kp < (int64_t)1 << 32) {
+    p.tiles_m = (int32_t)(R / bm);
+    p.tiles_n = (int32_t)(p.Np / 256);
+    const int64_t blocks = (int64_t)p.tiles_m * p.tiles_n;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    if (p.aq2)
+      hipLaunchKernelGGL((coded_gemm_fp8_wide_kernel<128, 2, 4, 1>), dim3((unsigned)blocks),
+                         dim3(wide8::NT), 0, stream, p);
+    else
+      hipLaunchKernelGGL((coded_gemm_fp8_wide_kernel<128, 2, 4, 0>), dim3((unsigned)blocks),
+                         dim3(wide8::NT), 0, stream, p);
+    return hipGetLastError();
+  }
   p.tiles_m = (int32_t)((p.Mb + 127) / 128);
   p.tiles_n = (int32_t)((p.N + 127) / 128);
   const int64_t blocks = (int64_t)p.n_sym * p.tiles_m * p.tiles_n;

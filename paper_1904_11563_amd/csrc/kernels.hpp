@@ -128,7 +128,8 @@ hipError_t launch_peel_grouped(const GroupDesc* d, const int64_t* pstart, int32_
 
 hipError_t launch_quant_a(const Fp8Params& p, hipStream_t stream);
 hipError_t launch_quant_b(const Fp8Params& p, hipStream_t stream);
-hipError_t launch_coded_gemm_fp8(const Fp8Params& p, hipStream_t stream);
+int32_t fp8_tile_count();
+hipError_t launch_coded_gemm_fp8(const Fp8Params& p, int32_t tile, hipStream_t stream);
 hipError_t launch_peel(const PeelParams& p, hipStream_t stream);
 hipError_t launch_encode(const EncodeParams& p, hipStream_t stream);
 

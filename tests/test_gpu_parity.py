@@ -443,6 +443,83 @@ def test_fp8_codes_and_scales_match_oracle():
             assert np.array_equal(bq[nb * 128:(nb + 1) * 128, kb * 128:(kb + 1) * 128], c.T)
 
 
+@pytest.mark.parametrize("prec", [bpx.PREC_FP8, bpx.PREC_FP8X2])
+def test_fp8_gemm_products_match_quantised_codes(prec):
+    """Each coded product of the FP8 GEMM, under both tilings (one 128x128
+    grid per symbol; 128x256 tiles over all symbols' codes), against the
+    same product formed in float64 from the oracle's codes and scales: per
+    128-wide k chunk, sA sB (qA . qB), with qA + qA2/16 for FP8x2, summed
+    over the chunks.  What separates them is the MFMA's own accumulation of
+    the 128 FP8 products of a chunk, which is not a sequence of IEEE FP32
+    additions (measured about 1.5e-5 relative on these operands), so the
+    bound is 1e-4, far below what a wrong index, scale or plane gives
+    (order 1).  The two tilings run the same MFMA sequence per output: FP8
+    results are bit-identical, FP8x2 (residual factor applied by the MFMA's
+    E8M0 scale in one tiling, by a multiply in the other) agree to 1e-6."""
+    from oracle import quant
+    code = code642()
+    oc = oracle_of(code)
+    M, K, N = 2048, 384, 512          # Mb = 256; N a multiple of 256
+    A = inputs.normal(24, inputs.TAG_A, (M, K))
+    B = inputs.normal(24, inputs.TAG_B, (K, N))
+    order = [5, 3, 0, 1, 2, 4]
+    plan = bpx.Plan(code, order, 0, bpx.MODE_FULL, M, K, N, prec)
+    sch = plan.schedule()
+    Mb = plan.info()["Mb"]
+    n_comp = plan.info()["n_computed"]
+    x2 = prec == bpx.PREC_FP8X2
+    Bh = np.zeros((K, N))
+    sB = {}
+    for kb in range(K // 128):
+        for nb in range(N // 128):
+            s, c = quant.quantize_block(B[kb * 128:(kb + 1) * 128, nb * 128:(nb + 1) * 128])
+            sB[kb, nb] = float(s)
+            Bh[kb * 128:(kb + 1) * 128, nb * 128:(nb + 1) * 128] = quant.e4m3_decode(c)
+    sym = {g: d for g, _, d in oc.symbols()}
+    refs = {}
+    for g in sch["computed"].tolist():
+        blk = quant.coded_block_fp32(A, Mb, sym[g], M)
+        ref = np.zeros((Mb, N))
+        for rb in range(Mb // 128):
+            for kb in range(K // 128):
+                t = blk[rb * 128:(rb + 1) * 128, kb * 128:(kb + 1) * 128]
+                if x2:
+                    s, c1, c2 = quant.quantize_block(t, residual=True)
+                    ah = quant.e4m3_decode(c1) + quant.e4m3_decode(c2) / 16.0
+                else:
+                    s, c1 = quant.quantize_block(t)
+                    ah = quant.e4m3_decode(c1)
+                for nb in range(N // 128):
+                    ref[rb * 128:(rb + 1) * 128, nb * 128:(nb + 1) * 128] += (
+                        float(s) * sB[kb, nb] *
+                        (ah @ Bh[kb * 128:(kb + 1) * 128, nb * 128:(nb + 1) * 128]))
+        refs[g] = ref
+    got = {}
+    for tile in (0, 1):
+        Cd = torch.zeros((M, N), device="cuda")
+        ws = bpx.alloc_workspace(plan)
+        try:
+            bpx.force_tile(tile)
+            bpx.coded_gemm(plan, dev(A), dev(B), Cd, ws)
+        finally:
+            bpx.force_tile(-1)
+        Y = host(ws)[:n_comp * Mb * N * 4].view(np.float32)
+        C = host(Cd)
+        for g, d in zip(sch["computed"].tolist(), sch["dest"].tolist()):
+            if d >= 0:
+                y = Y[d * Mb * N:(d + 1) * Mb * N].reshape(Mb, N).copy()
+            else:
+                y = C[(-1 - d) * Mb:(-d) * Mb].copy()
+            e = relf(y, refs[g])
+            assert e <= 1e-4, (g, tile, prec, e)
+            got[tile, g] = y
+    for g in sch["computed"].tolist():
+        if x2:
+            assert relf(got[1, g], got[0, g]) <= 1e-6, g
+        else:
+            assert np.array_equal(got[1, g], got[0, g]), g
+
+
 def test_fp8_mojette_end_to_end():
     """Mojette Construction A (k=16, n=24, b=8), 8 of 24 columns erased, at a
     reduced M, K, N: FP8x2 within 3e-2 of float64; 1-pass FP8 reported."""
