@@ -243,8 +243,8 @@ def run_single(args):
         f32_kernel = "coded_gemm_f32_kernel<64,128,32,2>"
     kernel = {"f32": f32_kernel, "bf16": "split_b + coded_gemm_bf16_kernel",
               "bf16x3": "split_b + coded_gemm_bf16_kernel",
-              "fp8": "quant_b + quant_a + coded_gemm_fp8_kernel",
-              "fp8x2": "quant_b + quant_a + coded_gemm_fp8_kernel"}[prec_name]
+              "fp8": "quant_b + quant_a + coded_gemm_fp8_wide_kernel, one call",
+              "fp8x2": "quant_b + quant_a + coded_gemm_fp8_wide_kernel, one call"}[prec_name]
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK[prec_name],
                 "unit": "TFLOP/s", "frac": achieved / PEAK[prec_name],
                 "traffic": load_traffic(w.name, prec_name), "kernel": kernel,
