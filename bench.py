@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-ref", action="store_true", help="skip the uncoded references")
+    ap.add_argument("--tile", type=int, default=-1,
+                    help="force one GEMM tile shape (bpx_force_tile) instead of the defaults")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="rough budget of the CPU oracle sample")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -127,6 +129,8 @@ def run_single(args):
     from paper_1904_11563_amd import autotune, bpx, inputs
 
     autotune.load()
+    if args.tile >= 0:
+        bpx.force_tile(args.tile)
     w = inputs.WORKLOADS[args.workload]
     prec_name = args.prec or ("fp8x2" if w.prec == "fp8" else w.prec)
     prec = bpx.PREC_NAMES[prec_name]
@@ -332,6 +336,8 @@ def run_batch(args):
     from paper_1904_11563_amd import autotune, bpx, inputs
 
     tuned = autotune.load()
+    if args.tile >= 0:
+        bpx.force_tile(args.tile)
     prec_name = args.prec or "bf16x3"
     prec = bpx.PREC_NAMES[prec_name]
     dev = torch.device("cuda:0")
@@ -421,7 +427,8 @@ def run_batch(args):
            "codes": "(6,4,2) for k=4, (12,8,2) for k=8 (searched)", "mode": "arrival",
            "mean_prefix_overhead": float(np.mean([m["n_computed"] * 1.0 /
                                                   (2 * s[3]) for m, s in zip(meta, shapes)])),
-           "tile_table": "autotuned" if tuned else "default", "graph": "hipGraph replay",
+           "tile_table": (f"forced {args.tile}" if args.tile >= 0 else
+                          "autotuned" if tuned else "default"), "graph": "hipGraph replay",
            "parallelism": "none (1 GPU)"}
     out = header(args, value, ms, prec_name, cfg)
     out.update({"rel_err": rel_err, "rel_err_sample": "8 rows x all columns of every product",

@@ -59,7 +59,9 @@ int32_t choose_tile(int32_t prec, int64_t Mb, int64_t N, int64_t K) {
     const int32_t t = g_tile_table[idx];
     if (t >= 0 && t < tile_count_for(prec)) return t;
   }
-  if (prec == BPX_PREC_BF16 || prec == BPX_PREC_BF16X3) return 1;  // 64x128, no spills
+  // BF16 / BF16x3 default: the flat-row 128x256 tiling (its callers fall
+  // back to 64x128 where K is not a multiple of 32)
+  if (prec == BPX_PREC_BF16 || prec == BPX_PREC_BF16X3) return 4;
   if (prec == BPX_PREC_FP8 || prec == BPX_PREC_FP8X2) return 1;    // wide tiling
   // FP32 default: the 256 x 256 tile with 4 x 2 waves (measured fastest on
   // 8192x8192x4096); its launcher takes the 64 x 128 tile for shapes that
@@ -322,12 +324,20 @@ bpx_status group_build(bpx_plan* const* plans, const float* const* A, const floa
                   ? reinterpret_cast<const unsigned short*>(planes + pl->bt_plane_bytes())
                   : nullptr;
     p.kp = pl->kp();
-    const int32_t t = choose_tile(prec, pl->Mb, pl->N, pl->K);
+    int32_t t = choose_tile(prec, pl->Mb, pl->N, pl->K);
+    if (bf16_tile_is_flat(t) && !bf16_flat_ok(p)) t = 1;
     const TileShape sh = bf16_tile_shape(t);
-    p.tiles_m = (int32_t)((pl->Mb + sh.bm - 1) / sh.bm);
-    p.tiles_n = (int32_t)((pl->N + sh.bn - 1) / sh.bn);
+    int64_t nt;
+    if (bf16_tile_is_flat(t)) {  // tiles over the stacked rows of all symbols
+      p.tiles_m = (int32_t)(((int64_t)p.n_sym * pl->Mb + sh.bm - 1) / sh.bm);
+      p.tiles_n = (int32_t)((pl->N + sh.bn - 1) / sh.bn);
+      nt = (int64_t)p.tiles_m * p.tiles_n;
+    } else {
+      p.tiles_m = (int32_t)((pl->Mb + sh.bm - 1) / sh.bm);
+      p.tiles_n = (int32_t)((pl->N + sh.bn - 1) / sh.bn);
+      nt = (int64_t)p.n_sym * p.tiles_m * p.tiles_n;
+    }
     d.tile = t;
-    const int64_t nt = (int64_t)p.n_sym * p.tiles_m * p.tiles_n;
     for (int64_t l = 0; l < nt; ++l) {
       by_tile[t].push_back(GroupTile{i, (int32_t)l});
       key[t].push_back(pl->K);

@@ -293,6 +293,234 @@ __device__ __forceinline__ void bf16_tile(const GemmParams& p, int si, int mt, i
   }
 }
 
+// ------------------------------------------------------------ flat tile --
+// The computed symbols' coded blocks, stacked, are one R x K matrix
+// (R = n_sym * Mb) whose row gr belongs to symbol gr / Mb; one R x N x K
+// product covers them all, so 128-row tiles span symbol boundaries and
+// small blocks waste no rows.  Each thread looks up the symbol and member
+// rows of the two A rows it stages; the encode sums the members in FP32 and
+// splits the sum into BF16 hi / lo while staging.  8 waves (2 x 4) of
+// 64 x 64, K-stages of 32, the next stage's loads in registers during the
+// current stage's MFMAs, LDS double buffer.  Rows past a product's end and B rows past N come back as zeros
+// from the buffer resources' range check.  Needs K a multiple of 32.
+namespace flat {
+constexpr int BM = 128, BN = 256, NT = 512;
+constexpr int TM = 64, TN = 64, FM = 4, FN = 4;  // wave tile (2 x 4 waves)
+constexpr int A_PLANE = BM * KS, B_PLANE = BN * KS;
+constexpr int UA = BM * BK / 4 / NT;        // float4 of A per thread per member (2)
+constexpr int UB = BN * BK * 2 / 16 / NT;   // 16-byte B chunks per thread per plane (2)
+constexpr int kRsrcWord3 = 0x00020000;      // gfx9 raw buffer, 32-bit elements
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0,
+                                           (int)(bytes > 0 ? bytes : 0), kRsrcWord3);
+}
+__device__ __forceinline__ v4f bload(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
+  return __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, 0, 0));
+}
+__device__ __forceinline__ v4u bload_u(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
+  return __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, 0, 0));
+}
+
+template <int SPLIT>
+constexpr int lds_elems() {
+  return 2 * (SPLIT == 3 ? 2 : 1) * (A_PLANE + B_PLANE);
+}
+}  // namespace flat
+
+template <int SPLIT>
+__device__ __forceinline__ void bf16_flat_tile(const GemmParams& p, int mt, int nt, us* lds) {
+  using namespace flat;
+  constexpr int NPL = SPLIT == 3 ? 2 : 1;
+  constexpr int STAGE = NPL * (A_PLANE + B_PLANE);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 2, wn = wave & 3;
+  const int q = lane >> 4, c16 = lane & 15;
+  const int64_t m0 = (int64_t)mt * BM, n0 = (int64_t)nt * BN;
+  const int64_t Mb = p.Mb, M = p.M, N = p.N, K = p.K, Kp = p.kp, lda = p.lda;
+  const int64_t R = (int64_t)p.n_sym * Mb;
+
+  // A: rows ar + 64 u of the tile, k ak .. ak+3 of the stage
+  const int ar = tid >> 3, ak = (tid & 7) * 4;
+  uint32_t off[UA][kPre];
+  int deg_u[UA], idoff_u[UA], lr_u[UA];
+#pragma unroll
+  for (int u = 0; u < UA; ++u) {
+    const int64_t gr = m0 + ar + 64 * u;
+    int deg = 0, id_off = 0;
+    int64_t lr = 0;
+    if (gr < R) {
+      const int64_t si = gr / Mb;
+      lr = gr - si * Mb;
+      id_off = p.syms[4 * si + 0];
+      deg = p.syms[4 * si + 1];
+    }
+    deg_u[u] = deg;
+    idoff_u[u] = id_off;
+    lr_u[u] = (int)lr;
+#pragma unroll
+    for (int m = 0; m < kPre; ++m)
+      off[u][m] = m < deg ? (uint32_t)((((int64_t)p.ids[id_off + m] * Mb + lr) * lda + ak) * 4)
+                          : 0u;
+  }
+  // B: chunk c -> tile row n = f / 4, k offset (f % 4) * 8, f = tid + NT c
+  uint32_t boff[UB];
+#pragma unroll
+  for (int c = 0; c < UB; ++c) {
+    const int f = tid + NT * c;
+    boff[c] = (uint32_t)(((n0 + (f >> 2)) * Kp + (f & 3) * 8) * 2);
+  }
+
+  v4f preA[kPre][UA];
+  v4u brA[NPL][UB];
+  auto load = [&](v4f (&pre)[kPre][UA], v4u (&bre)[NPL][UB], int k0)
+                  __attribute__((always_inline)) {
+    const auto ra = rsrc(p.A + k0, (M * lda - k0) * 4);
+#pragma unroll
+    for (int u = 0; u < UA; ++u)
+#pragma unroll
+      for (int m = 0; m < kPre; ++m) {
+        v4f v = {0.f, 0.f, 0.f, 0.f};
+        if (m < deg_u[u]) v = bload(ra, off[u][m]);
+        pre[m][u] = v;
+      }
+#pragma unroll
+    for (int pl = 0; pl < NPL; ++pl) {
+      const auto rb = rsrc((pl == 0 ? p.bt_hi : p.bt_lo) + k0, (N * Kp - k0) * 2);
+#pragma unroll
+      for (int c = 0; c < UB; ++c) bre[pl][c] = bload_u(rb, boff[c]);
+    }
+  };
+  auto store = [&](v4f (&pre)[kPre][UA], v4u (&bre)[NPL][UB], int buf, int k0)
+                   __attribute__((always_inline)) {
+    us* st = lds + buf * STAGE;
+#pragma unroll
+    for (int u = 0; u < UA; ++u) {
+      v4f sum = pre[0][u];
+#pragma unroll
+      for (int m = 1; m < kPre; ++m) sum += pre[m][u];
+      for (int m = kPre; m < deg_u[u]; ++m) {  // members beyond the prefetch depth
+        const int64_t row = (int64_t)p.ids[idoff_u[u] + m] * Mb + lr_u[u];
+        if (row < M) sum += *reinterpret_cast<const v4f*>(p.A + row * lda + k0 + ak);
+      }
+      const v4bf hi = to_bf16(sum);
+      *reinterpret_cast<v4bf*>(st + (ar + 64 * u) * KS + ak) = hi;
+      if (SPLIT == 3)
+        *reinterpret_cast<v4bf*>(st + A_PLANE + (ar + 64 * u) * KS + ak) =
+            to_bf16(sum - from_bf16(hi));
+    }
+    us* Bs = st + NPL * A_PLANE;
+#pragma unroll
+    for (int pl = 0; pl < NPL; ++pl)
+#pragma unroll
+      for (int c = 0; c < UB; ++c) {
+        const int f = tid + NT * c;
+        *reinterpret_cast<v4u*>(Bs + pl * B_PLANE + (f >> 2) * KS + (f & 3) * 8) = bre[pl][c];
+      }
+  };
+
+  v4f acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  auto compute = [&](int buf) __attribute__((always_inline)) {
+    const us* st = lds + buf * STAGE;
+    const us* Bs = st + NPL * A_PLANE;
+    v8bf ah[FM], al[FM];
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+      const int r = wm * TM + i * 16 + c16;
+      ah[i] = *reinterpret_cast<const v8bf*>(st + r * KS + 8 * q);
+      if (SPLIT == 3) al[i] = *reinterpret_cast<const v8bf*>(st + A_PLANE + r * KS + 8 * q);
+    }
+    // one output column group at a time keeps two B fragments live
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int n = wn * TN + 4 * c16 + j;  // interleaved output columns
+      const v8bf bh = *reinterpret_cast<const v8bf*>(Bs + n * KS + 8 * q);
+      if (SPLIT == 3) {
+        const v8bf bl = *reinterpret_cast<const v8bf*>(Bs + B_PLANE + n * KS + 8 * q);
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+    }
+  };
+
+  const int nk = (int)(K / BK);
+  load(preA, brA, 0);
+  store(preA, brA, 0, 0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const bool more = kt + 1 < nk;
+    if (more) load(preA, brA, (kt + 1) * BK);
+    compute(kt & 1);
+    if (more) store(preA, brA, (kt + 1) & 1, (kt + 1) * BK);
+    __syncthreads();
+  }
+
+  const bool vec_ok = (p.ldc & 3) == 0 && (N & 3) == 0;
+  const int64_t col = n0 + wn * TN + 4 * c16;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t gr = m0 + wm * TM + i * 16 + 4 * q + r;
+      if (gr >= R) continue;
+      const int64_t si = gr / Mb;
+      const int64_t lr = gr - si * Mb;
+      const int dest = p.syms[4 * si + 2];
+      float* dst;
+      bool vec = vec_ok;
+      if (dest >= 0) {
+        dst = p.Y + ((int64_t)dest * Mb + lr) * N + col;
+      } else {
+        const int64_t row = (-1 - (int64_t)dest) * Mb + lr;
+        if (row >= M) continue;
+        dst = p.C + row * p.ldc + col;
+      }
+      const v4f v = {acc[i][0][r], acc[i][1][r], acc[i][2][r], acc[i][3][r]};
+      if (col + 3 < N && vec) {
+        *reinterpret_cast<v4f*>(dst) = v;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (col + e < N) dst[e] = v[e];
+      }
+    }
+}
+
+template <int SPLIT>
+__global__ __launch_bounds__(flat::NT, 1) void coded_gemm_bf16_flat_kernel(GemmParams p) {
+  __shared__ __attribute__((aligned(16))) us lds[flat::lds_elems<SPLIT>()];
+  const int lin = xcd_remap(blockIdx.x, gridDim.x);
+  const int mt = lin / p.tiles_n;
+  bf16_flat_tile<SPLIT>(p, mt, lin - mt * p.tiles_n, lds);
+}
+
+// Persistent grouped form of the flat tile (GroupTile.lin = mt * tiles_n + nt).
+template <int SPLIT>
+__global__ __launch_bounds__(flat::NT, 1) void gemm_bf16_flat_grouped_kernel(
+    const GroupDesc* d, const GroupTile* tiles, int32_t n_tiles) {
+  __shared__ __attribute__((aligned(16))) us lds[flat::lds_elems<SPLIT>()];
+  for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const GroupTile gt = tiles[t];
+    const GemmParams& p = d[gt.prod].g;
+    const int mt = gt.lin / p.tiles_n;
+    bf16_flat_tile<SPLIT>(p, mt, gt.lin - mt * p.tiles_n, lds);
+    __syncthreads();  // the next tile's prologue overwrites LDS stage 0
+  }
+}
+
 template <int BM, int BN, int SPLIT>
 constexpr int bf16_lds_elems() {
   using T = Bf16Tile<BM, BN>;
@@ -368,18 +596,28 @@ struct Bf16Entry {
   void (*k1)(GemmParams);
   void (*k3)(GemmParams);
 };
+constexpr int32_t kBf16Flat = 4;
 
 const Bf16Entry kBf16Tiles[] = {
     {{128, 128, 32}, coded_gemm_bf16_kernel<128, 128, 1, 2>, coded_gemm_bf16_kernel<128, 128, 3, 2>},
     {{64, 128, 32}, coded_gemm_bf16_kernel<64, 128, 1, 2>, coded_gemm_bf16_kernel<64, 128, 3, 2>},
     {{128, 256, 32}, coded_gemm_bf16_kernel<128, 256, 1, 1>, coded_gemm_bf16_kernel<128, 256, 3, 1>},
     {{64, 256, 32}, coded_gemm_bf16_kernel<64, 256, 1, 1>, coded_gemm_bf16_kernel<64, 256, 3, 1>},
+    // flat rows over all symbols (tiles_m counts 128-row tiles of n_sym * Mb)
+    {{128, 256, 32}, coded_gemm_bf16_flat_kernel<1>, coded_gemm_bf16_flat_kernel<3>},
 };
 
 }  // namespace
 
 int32_t bf16_tile_count() { return (int32_t)(sizeof(kBf16Tiles) / sizeof(kBf16Tiles[0])); }
 TileShape bf16_tile_shape(int32_t t) { return kBf16Tiles[t].shape; }
+bool bf16_tile_is_flat(int32_t t) { return t == kBf16Flat; }
+
+bool bf16_flat_ok(const GemmParams& p) {
+  const int64_t lim = (int64_t)1 << 31;
+  return p.K % 32 == 0 && p.kp == p.K && (p.M + p.Mb) * p.lda * 4 < lim &&
+         p.N * p.kp * 2 < lim && (int64_t)p.n_sym * p.Mb < lim;
+}
 
 hipError_t launch_split_b(const float* B, int64_t ldb, int64_t K, int64_t N, int64_t Kp,
                           void* bt_hi, void* bt_lo, hipStream_t stream) {
@@ -402,6 +640,15 @@ hipError_t launch_gemm_bf16_grouped(const GroupDesc* d, const GroupTile* tiles, 
                                     int32_t tile, int32_t split, int32_t grid,
                                     hipStream_t stream) {
   if (n_tiles == 0) return hipSuccess;
+  if (tile == kBf16Flat) {
+    if (split == 3)
+      hipLaunchKernelGGL(gemm_bf16_flat_grouped_kernel<3>, dim3((unsigned)grid), dim3(flat::NT),
+                         0, stream, d, tiles, n_tiles);
+    else
+      hipLaunchKernelGGL(gemm_bf16_flat_grouped_kernel<1>, dim3((unsigned)grid), dim3(flat::NT),
+                         0, stream, d, tiles, n_tiles);
+    return hipGetLastError();
+  }
   void (*k)(const GroupDesc*, const GroupTile*, int32_t) = nullptr;
   switch (tile * 4 + split) {
     case 0 * 4 + 1: k = gemm_bf16_grouped_kernel<128, 128, 1>; break;
@@ -420,6 +667,20 @@ hipError_t launch_gemm_bf16_grouped(const GroupDesc* d, const GroupTile* tiles, 
 
 hipError_t launch_coded_gemm_bf16(const GemmParams& p0, int32_t tile, hipStream_t stream) {
   GemmParams p = p0;
+  if (tile == kBf16Flat) {
+    if (bf16_flat_ok(p)) {
+      p.tiles_m = (int32_t)(((int64_t)p.n_sym * p.Mb + flat::BM - 1) / flat::BM);
+      p.tiles_n = (int32_t)((p.N + flat::BN - 1) / flat::BN);
+      const int64_t blocks = (int64_t)p.tiles_m * p.tiles_n;
+      if (blocks == 0) return hipSuccess;
+      if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+      hipLaunchKernelGGL(p.prec == BPX_PREC_BF16X3 ? coded_gemm_bf16_flat_kernel<3>
+                                                   : coded_gemm_bf16_flat_kernel<1>,
+                         dim3((unsigned)blocks), dim3(flat::NT), 0, stream, p);
+      return hipGetLastError();
+    }
+    tile = 1;  // K not a multiple of 32, or offsets past 31 bits
+  }
   const Bf16Entry& e = kBf16Tiles[tile];
   p.tiles_m = (int32_t)((p.Mb + e.shape.bm - 1) / e.shape.bm);
   p.tiles_n = (int32_t)((p.N + e.shape.bn - 1) / e.shape.bn);

@@ -96,6 +96,10 @@ hipError_t launch_coded_gemm(const GemmParams& p, int32_t tile, hipStream_t stre
 
 int32_t bf16_tile_count();
 TileShape bf16_tile_shape(int32_t t);
+// Tile 4 is the flat-row tiling (tiles over all symbols' stacked rows); it
+// needs K a multiple of 32 and offsets within 31 bits (bf16_flat_ok).
+bool bf16_tile_is_flat(int32_t t);
+bool bf16_flat_ok(const GemmParams& p);
 // Bt_hi[n][k] = bf16(B[k][n]), Bt_lo = bf16(B - Bt_hi) (bt_lo may be null),
 // zero for k in [K, Kp).
 hipError_t launch_split_b(const float* B, int64_t ldb, int64_t K, int64_t N, int64_t Kp,

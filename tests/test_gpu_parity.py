@@ -353,6 +353,58 @@ def test_bf16_integer_operands_exact(prec):
         assert np.array_equal(C.astype(np.float64), R), (prec, lost)
 
 
+@pytest.mark.parametrize("prec", [bpx.PREC_BF16, bpx.PREC_BF16X3])
+def test_bf16_flat_tile_exact_and_identical_to_per_symbol_tile(prec):
+    """The flat-row BF16 tiling (128x256 tiles over the stacked rows of all
+    symbols, tiles crossing symbol boundaries) on a ragged shape: integer
+    operands decode exactly; float operands give the same bits as the
+    per-symbol 64x128 tiling (same k order and same MFMA order per
+    output)."""
+    code = code642()
+    M, K, N = 517, 256, 300          # Mb = 65: tiles straddle symbols
+    order = [5, 3, 0, 1, 2, 4]
+    plan = bpx.Plan(code, order, 0, bpx.MODE_STRAGGLER, M, K, N, prec)
+    A = inputs.integers(31, inputs.TAG_A, (M, K))
+    B = inputs.integers(31, inputs.TAG_B, (K, N))
+    Af = inputs.normal(31, inputs.TAG_A, (M, K))
+    Bf = inputs.normal(31, inputs.TAG_B, (K, N))
+    try:
+        bpx.force_tile(4)
+        C = run(plan, A, B)
+        assert np.array_equal(C.astype(np.float64), A.astype(np.float64) @ B.astype(np.float64))
+        Cf4 = run(plan, Af, Bf)
+        bpx.force_tile(1)
+        Cf1 = run(plan, Af, Bf)
+    finally:
+        bpx.force_tile(-1)
+    assert np.array_equal(Cf4, Cf1)
+
+
+def test_grouped_flat_tile_exact_and_identical_to_per_symbol_tile():
+    """The grouped launch with every product on the flat-row tiling: integer
+    operands bit exact, float operands bit-identical to the per-symbol
+    tiling."""
+    outs = {}
+    for tile in (4, 1):
+        for integer in (True, False):
+            try:
+                bpx.force_tile(tile)
+                plans, As, Bs, Cs, ws, ops = _group_case(5, 16, integer, mult=32)
+                g = bpx.Group(plans, As, Bs, Cs, ws)
+            finally:
+                bpx.force_tile(-1)
+            g.launch()
+            torch.cuda.synchronize()
+            outs[tile, integer] = [host(c) for c in Cs]
+            if integer:
+                for (A, B), C in zip(ops, outs[tile, integer]):
+                    assert np.array_equal(C.astype(np.float64),
+                                          A.astype(np.float64) @ B.astype(np.float64))
+            del g
+    for a, b in zip(outs[4, False], outs[1, False]):
+        assert np.array_equal(a, b)
+
+
 def test_bf16x3_row_scaled_workload():
     """512^3, A rows scaled log-uniformly in [1e-3, 1e3], (6,4,2) code with two
     erased columns: split-BF16x3 must stay within 1e-5 of float64."""
@@ -560,11 +612,11 @@ def test_fp8_integer_operands_small_chain():
 
 # ---------------------------------------------------------- grouped path --
 
-def _group_case(seed, count, integer):
+def _group_case(seed, count, integer, mult=4):
     """count products with shapes from the batch generator (scaled down),
     codes (6,4,2) or (12,8,2) by k, own seeded erasure patterns."""
     codes_by_k = {4: code642(), 8: lib_code(inputs.CODE_1282)}
-    shapes = inputs.batch_shapes(seed, count, lo=128, hi=640, mult=4)
+    shapes = inputs.batch_shapes(seed, count, lo=128, hi=640, mult=mult)
     plans, As, Bs, Cs, host_ops = [], [], [], [], []
     for i, (M, K, N, k) in enumerate(shapes):
         code = codes_by_k[k]
