@@ -269,6 +269,26 @@ def run_single(args):
     return out
 
 
+def peel_bytes(plan, M, N):
+    """Algorithmic (read, write) bytes of a plan's peel: a block whose
+    releaser's product went to a workspace slot is read there and written to
+    C; a block released into C in place is read only if a later release
+    subtracts it."""
+    sch = plan.schedule()
+    Mb = plan.info()["Mb"]
+    rows = lambda s: max(0, min(Mb, M - s * Mb))
+    dest = dict(zip(sch["computed"].tolist(), sch["dest"].tolist()))
+    used = set(sch["sub_data"].tolist())
+    rd = wr = 0
+    for s, g in enumerate(sch["releaser"].tolist()):
+        d = dest[g]
+        if d >= 0 or s in used:
+            rd += rows(s) * N * 4
+        if d >= 0:
+            wr += rows(s) * N * 4
+    return rd, wr
+
+
 def hbm_kernels(torch, bpx, plan, code, Ad, Cd, ws, w, info, steps):
     """Achieved HBM GB/s of the two streaming kernels: the standalone encode
     (bpx_encode) and the peel, each as algorithmic bytes / event time."""
@@ -284,15 +304,7 @@ def hbm_kernels(torch, bpx, plan, code, Ad, Cd, ws, w, info, steps):
     bpx.encode(plan, Ad, out_enc)
     enc_ms = timed(torch, lambda: bpx.encode(plan, Ad, out_enc), steps)
     del out_enc
-    dest = dict(zip(comp, sch["dest"].tolist()))
-    used = set(sch["sub_data"].tolist())
-    rd = wr = 0
-    for s, g in enumerate(sch["releaser"].tolist()):
-        d = dest[g]
-        if d >= 0 or s in used:
-            rd += rows(s) * N * 4
-        if d >= 0:
-            wr += rows(s) * N * 4
+    rd, wr = peel_bytes(plan, M, N)
     peel_ms = timed(torch, lambda: bpx.peel_decode(plan, ws, Cd), steps)
     res = {"peak_GBps": 8000.0}
     for name, b, t in (("encode", enc_read + enc_write, enc_ms), ("peel", rd + wr, peel_ms)):
@@ -393,8 +405,19 @@ def run_batch(args):
     phase_ms = [timed(torch, lambda p=p: group.launch_phase(p), max(3, args.steps // 3))
                 for p in range(3)]
     comp_flops = 0.0
-    for (M, K, N, k), inf in zip(shapes, meta):
+    split_bytes = peel_rd = peel_wr = 0
+    planes = 2 if prec_name == "bf16x3" else 1
+    for (M, K, N, k), inf, pl in zip(shapes, meta, plans):
         comp_flops += 2.0 * inf["Mb"] * K * N * inf["n_computed"]
+        split_bytes += K * N * 4 + N * (-(-K // 32) * 32) * 2 * planes
+        r, wb = peel_bytes(pl, M, N)
+        peel_rd += r
+        peel_wr += wb
+    hbm = {"peak_GBps": 8000.0}
+    for name, b, t in (("split_b", split_bytes, phase_ms[0]),
+                       ("peel", peel_rd + peel_wr, phase_ms[2])):
+        hbm[name] = {"bytes": b, "ms": t, "GBps": b / (t * 1e-3) / 1e9,
+                     "frac": b / (t * 1e-3) / 1e9 / 8000.0}
     achieved = comp_flops / (phase_ms[1] * 1e-3) / 1e12
 
     refs = {}
@@ -437,8 +460,9 @@ def run_batch(args):
                 "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[prec_name],
                              "unit": "TFLOP/s", "frac": achieved / PEAK[prec_name],
                              "traffic": load_traffic("batch", prec_name),
-                             "kernel": "gemm_bf16_grouped_kernel",
-                             "flops_per_launch": comp_flops, "launch_ms": phase_ms[1]}})
+                             "kernel": "gemm_bf16_flat_grouped_kernel (GEMM phase)",
+                             "flops_per_launch": comp_flops, "launch_ms": phase_ms[1]},
+                "hbm": hbm})
     out.update(refs)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_batch(shapes, plans, codes, As, Bs, args)

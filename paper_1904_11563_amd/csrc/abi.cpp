@@ -225,6 +225,7 @@ bpx_status peel_impl(bpx_plan* plan, const void* ws, size_t ws_bytes, float* C, 
   p.subs = plan->d_step_subs;
   p.nsteps = (int32_t)plan->steps.size();
   p.nslots = plan->n_lds_slots;
+  p.nsubs = (int32_t)plan->step_subs.size();
   hipError_t e = launch_peel(p, stream);
   if (e == hipErrorInvalidConfiguration)
     return fail(BPX_E_UNSUPPORTED, "peel needs more LDS than a workgroup has");
@@ -253,8 +254,11 @@ struct bpx_group {
   const int64_t* d_bstart = nullptr;
   const int64_t* d_pstart = nullptr;
   const bpx::GroupTile* d_tiles = nullptr;
+  const int32_t* d_bmap = nullptr;  // product of each split-B block
+  const int32_t* d_pmap = nullptr;  // product of each peel block
   int64_t total_b = 0, total_p = 0;
   int32_t max_slots = 0;
+  size_t max_program = 0;
   std::vector<bpx::GroupLaunch> launches;
 };
 
@@ -298,6 +302,7 @@ bpx_status group_build(bpx_plan* const* plans, const float* const* A, const floa
   char* w = static_cast<char*>(ws);
   int64_t tb = 0, tp = 0;
   int32_t max_slots = 0;
+  size_t max_program = 0;
   for (int32_t i = 0; i < count; ++i) {
     bpx_plan* pl = plans[i];
     GroupDesc& d = desc[i];
@@ -353,6 +358,8 @@ bpx_status group_build(bpx_plan* const* plans, const float* const* A, const floa
     pe.subs = pl->d_step_subs;
     pe.nsteps = (int32_t)pl->steps.size();
     pe.nslots = pl->n_lds_slots;
+    pe.nsubs = (int32_t)pl->step_subs.size();
+    max_program = std::max(max_program, peel_program_bytes(pe.nsteps, pe.nsubs));
     max_slots = std::max(max_slots, pl->n_lds_slots);
     d.b_tn = (int32_t)((pl->N + 63) / 64);
     d.b_tk = (int32_t)((pl->kp() + 63) / 64);
@@ -362,7 +369,7 @@ bpx_status group_build(bpx_plan* const* plans, const float* const* A, const floa
     if (pe.nsteps > 0) tp += (pl->Mb * (pl->N / 4) + 127) / 128;
     w += bpx_plan::align256(pl->ws_bytes());
   }
-  if ((size_t)max_slots * 128 * 16 > 160 * 1024)
+  if ((size_t)max_slots * 128 * 16 + max_program > 160 * 1024)
     return fail(BPX_E_UNSUPPORTED, "peel needs more LDS than a workgroup has");
   // tile lists: longest K first (stable), one persistent launch per shape
   std::vector<GroupTile> tiles;
@@ -380,17 +387,29 @@ bpx_status group_build(bpx_plan* const* plans, const float* const* A, const floa
     L.grid = std::min(L.n, slots);
     launches.push_back(L);
   }
-  // one device block: descriptors | bstart | pstart | tiles
+  // block -> product maps of the split-B and peel grids
+  std::vector<int32_t> bmap(tb), pmap(tp);
+  for (int32_t i = 0; i < count; ++i) {
+    const int64_t bend = i + 1 < count ? bstart[i + 1] : tb;
+    const int64_t pend = i + 1 < count ? pstart[i + 1] : tp;
+    for (int64_t b = bstart[i]; b < bend; ++b) bmap[b] = i;
+    for (int64_t b = pstart[i]; b < pend; ++b) pmap[b] = i;
+  }
+  // one device block: descriptors | bstart | pstart | tiles | bmap | pmap
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   const size_t s0 = al(desc.size() * sizeof(GroupDesc));
   const size_t s1 = al(bstart.size() * 8);
   const size_t s2 = al(pstart.size() * 8);
   const size_t s3 = al(std::max<size_t>(tiles.size(), 1) * sizeof(GroupTile));
-  std::string host(s0 + s1 + s2 + s3, '\0');
+  const size_t s4 = al(std::max<size_t>(bmap.size(), 1) * 4);
+  const size_t s5 = al(std::max<size_t>(pmap.size(), 1) * 4);
+  std::string host(s0 + s1 + s2 + s3 + s4 + s5, '\0');
   std::memcpy(&host[0], desc.data(), desc.size() * sizeof(GroupDesc));
   std::memcpy(&host[s0], bstart.data(), bstart.size() * 8);
   std::memcpy(&host[s0 + s1], pstart.data(), pstart.size() * 8);
   std::memcpy(&host[s0 + s1 + s2], tiles.data(), tiles.size() * sizeof(GroupTile));
+  std::memcpy(&host[s0 + s1 + s2 + s3], bmap.data(), bmap.size() * 4);
+  std::memcpy(&host[s0 + s1 + s2 + s3 + s4], pmap.data(), pmap.size() * 4);
   void* dptr = nullptr;
   hipError_t e = hipMalloc(&dptr, host.size());
   if (e != hipSuccess) return hip_fail(e, "hipMalloc(group descriptors)");
@@ -410,9 +429,12 @@ bpx_status group_build(bpx_plan* const* plans, const float* const* A, const floa
   g->d_bstart = reinterpret_cast<const int64_t*>(base + s0);
   g->d_pstart = reinterpret_cast<const int64_t*>(base + s0 + s1);
   g->d_tiles = reinterpret_cast<const GroupTile*>(base + s0 + s1 + s2);
+  g->d_bmap = reinterpret_cast<const int32_t*>(base + s0 + s1 + s2 + s3);
+  g->d_pmap = reinterpret_cast<const int32_t*>(base + s0 + s1 + s2 + s3 + s4);
   g->total_b = tb;
   g->total_p = tp;
   g->max_slots = max_slots;
+  g->max_program = max_program;
   g->launches = launches;
   return BPX_OK;
 }
@@ -420,7 +442,7 @@ bpx_status group_build(bpx_plan* const* plans, const float* const* A, const floa
 bpx_status group_launch(bpx_group* g, int32_t phase, hipStream_t stream) {
   hipError_t e;
   if (phase < 0 || phase == 0) {
-    e = launch_split_b_grouped(g->d_desc, g->d_bstart, g->count, g->total_b, stream);
+    e = launch_split_b_grouped(g->d_desc, g->d_bstart, g->d_bmap, g->total_b, stream);
     if (e != hipSuccess) return hip_fail(e, "grouped split-B launch");
   }
   if (phase < 0 || phase == 1) {
@@ -432,7 +454,8 @@ bpx_status group_launch(bpx_group* g, int32_t phase, hipStream_t stream) {
     }
   }
   if (phase < 0 || phase == 2) {
-    e = launch_peel_grouped(g->d_desc, g->d_pstart, g->count, g->total_p, g->max_slots, stream);
+    e = launch_peel_grouped(g->d_desc, g->d_pstart, g->d_pmap, g->total_p, g->max_slots,
+                            g->max_program, stream);
     if (e != hipSuccess) return hip_fail(e, "grouped peel launch");
   }
   return BPX_OK;

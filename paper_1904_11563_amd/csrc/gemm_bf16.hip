@@ -539,36 +539,62 @@ __global__ __launch_bounds__(kThreads, OCC) void coded_gemm_bf16_kernel(GemmPara
   bf16_tile<BM, BN, SPLIT>(p, si, mt, nt, lds);
 }
 
-// Grouped split-B: a flat range of 64 x 64 transpose blocks over products.
+// Grouped split-B: a flat range of 64 x 64 transpose blocks over products
+// (bmap gives each block's product); float4 reads along n, 16-byte writes of
+// eight bf16 along k.
 __global__ __launch_bounds__(256) void split_b_grouped_kernel(const GroupDesc* d,
-                                                              const int64_t* bstart, int32_t count) {
+                                                              const int64_t* bstart,
+                                                              const int32_t* bmap) {
   const int64_t b = blockIdx.x;
-  int lo = 0, hi = count - 1;  // last product with bstart <= b
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) / 2;
-    if (bstart[mid] <= b) lo = mid; else hi = mid - 1;
-  }
+  const int lo = bmap[b];
   const GroupDesc& g = d[lo];
   const int64_t r = b - bstart[lo];
   const int64_t k0 = (r / g.b_tn) * 64, n0 = (r % g.b_tn) * 64;
   __shared__ float t[64][65];
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const int64_t K = g.g.K, N = g.g.N, Kp = g.g.kp;
-  for (int rr = ty; rr < 64; rr += 4) {
-    const int64_t k = k0 + rr, n = n0 + tx;
-    t[rr][tx] = (k < K && n < N) ? g.g.B[k * g.g.ldb + n] : 0.f;
+  const int tid = threadIdx.x;
+  const int64_t K = g.g.K, N = g.g.N, Kp = g.g.kp, ldb = g.g.ldb;
+  // read: thread owns float4 (row kr, columns nc .. nc+3), four rows apart
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int f = tid + 256 * i;
+    const int kr = f >> 4, nc = (f & 15) * 4;
+    const int64_t k = k0 + kr, n = n0 + nc;
+    v4f v = {0.f, 0.f, 0.f, 0.f};
+    if (k < K) {
+      const float* src = g.g.B + k * ldb + n;
+      if (n + 3 < N) {
+        v = *reinterpret_cast<const v4f*>(src);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (n + e < N) v[e] = src[e];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) t[kr][nc + e] = v[e];
   }
   __syncthreads();
-  us* hi_p = const_cast<us*>(g.g.bt_hi);
-  us* lo_p = const_cast<us*>(g.g.bt_lo);
-  for (int rr = ty; rr < 64; rr += 4) {
-    const int64_t n = n0 + rr, k = k0 + tx;
-    if (n < N && k < Kp) {
-      const float x = t[tx][rr];
-      const __bf16 h = (__bf16)x;
-      hi_p[n * Kp + k] = __builtin_bit_cast(us, h);
-      if (lo_p) lo_p[n * Kp + k] = __builtin_bit_cast(us, (__bf16)(x - (float)h));
-    }
+  // write: thread owns output row n = tid / 4, k kq .. kq+15 (two 16-byte
+  // pieces per plane)
+  const int nl = tid >> 2, kq = (tid & 3) * 16;
+  const int64_t n = n0 + nl, k = k0 + kq;
+  if (n >= N || k >= Kp) return;
+  unsigned hw[8], lw[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const float x0 = t[kq + 2 * j][nl], x1 = t[kq + 2 * j + 1][nl];
+    const __bf16 h0 = (__bf16)x0, h1 = (__bf16)x1;
+    const __bf16 l0 = (__bf16)(x0 - (float)h0), l1 = (__bf16)(x1 - (float)h1);
+    hw[j] = (unsigned)__builtin_bit_cast(us, h0) | ((unsigned)__builtin_bit_cast(us, h1) << 16);
+    lw[j] = (unsigned)__builtin_bit_cast(us, l0) | ((unsigned)__builtin_bit_cast(us, l1) << 16);
+  }
+  uint4* hp = reinterpret_cast<uint4*>(const_cast<us*>(g.g.bt_hi) + n * Kp + k);
+  hp[0] = uint4{hw[0], hw[1], hw[2], hw[3]};
+  hp[1] = uint4{hw[4], hw[5], hw[6], hw[7]};
+  if (g.g.bt_lo) {
+    uint4* lp = reinterpret_cast<uint4*>(const_cast<us*>(g.g.bt_lo) + n * Kp + k);
+    lp[0] = uint4{lw[0], lw[1], lw[2], lw[3]};
+    lp[1] = uint4{lw[4], lw[5], lw[6], lw[7]};
   }
 }
 
@@ -627,12 +653,12 @@ hipError_t launch_split_b(const float* B, int64_t ldb, int64_t K, int64_t N, int
   return hipGetLastError();
 }
 
-hipError_t launch_split_b_grouped(const GroupDesc* d, const int64_t* bstart, int32_t count,
+hipError_t launch_split_b_grouped(const GroupDesc* d, const int64_t* bstart, const int32_t* bmap,
                                   int64_t total_blocks, hipStream_t stream) {
   if (total_blocks == 0) return hipSuccess;
   if (total_blocks > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL(split_b_grouped_kernel, dim3((unsigned)total_blocks), dim3(256), 0, stream,
-                     d, bstart, count);
+                     d, bstart, bmap);
   return hipGetLastError();
 }
 

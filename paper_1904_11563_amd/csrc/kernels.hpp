@@ -72,7 +72,14 @@ struct PeelParams {
   const int32_t* subs;
   int32_t nsteps;
   int32_t nslots;
+  int32_t nsubs;  // length of subs
+  int32_t pad;
 };
+// Bytes of LDS a peel workgroup holds besides its slots: the step program
+// (steps, then subs), staged once per workgroup.
+inline size_t peel_program_bytes(int32_t nsteps, int32_t nsubs) {
+  return ((size_t)nsteps * sizeof(PeelStep) + (size_t)nsubs * 4 + 15) / 16 * 16;
+}
 
 // Standalone encode: out block i (Mb x K, ld K) = sum of member blocks of A.
 struct EncodeParams {
@@ -119,16 +126,19 @@ struct GroupTile {
   int32_t prod;
   int32_t lin;
 };
-// Grouped split-B: blocks [bstart[i], bstart[i+1]) belong to product i.
-hipError_t launch_split_b_grouped(const GroupDesc* d, const int64_t* bstart, int32_t count,
+// Grouped split-B: block b belongs to product bmap[b] and is block
+// b - bstart[bmap[b]] of that product's grid.
+hipError_t launch_split_b_grouped(const GroupDesc* d, const int64_t* bstart, const int32_t* bmap,
                                   int64_t total_blocks, hipStream_t stream);
 // Persistent grouped BF16 / BF16x3 GEMM over a tile list of one tile shape.
 hipError_t launch_gemm_bf16_grouped(const GroupDesc* d, const GroupTile* tiles, int32_t n_tiles,
                                     int32_t tile, int32_t split, int32_t grid,
                                     hipStream_t stream);
-// Grouped peel: blocks [pstart[i], pstart[i+1]) belong to product i.
-hipError_t launch_peel_grouped(const GroupDesc* d, const int64_t* pstart, int32_t count,
-                               int64_t total_blocks, int32_t max_slots, hipStream_t stream);
+// Grouped peel: block b belongs to product pmap[b] and is block
+// b - pstart[pmap[b]] of that product's peel grid.
+hipError_t launch_peel_grouped(const GroupDesc* d, const int64_t* pstart, const int32_t* pmap,
+                               int64_t total_blocks, int32_t max_slots, size_t max_program,
+                               hipStream_t stream);
 
 hipError_t launch_quant_a(const Fp8Params& p, hipStream_t stream);
 hipError_t launch_quant_b(const Fp8Params& p, hipStream_t stream);

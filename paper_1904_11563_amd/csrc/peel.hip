@@ -14,7 +14,10 @@
 // Two forms: a vector form (N and ldc multiples of 4) where a thread owns
 // four adjacent columns and moves 16 bytes per load and store, and a scalar
 // form for ragged N.  Loads of kBatch steps are issued before their
-// arithmetic so that many requests are in flight per thread.
+// arithmetic so that many requests are in flight per thread.  The program
+// (steps and subtrahend slot lists) is the same for every thread, so each
+// workgroup copies it to LDS once, behind its slots; the step loop then
+// reads descriptors from LDS instead of chasing them through global memory.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -31,9 +34,20 @@ __device__ __forceinline__ int64_t valid_rows(const PeelParams& p, int64_t base)
   return p.M - base < p.Mb ? p.M - base : p.Mb;
 }
 
+// Copies the step program to LDS (prog = steps, then subs); returns after a
+// barrier, so every thread of the workgroup sees it.
+__device__ __forceinline__ void stage_program(const PeelParams& p, int32_t* prog, int nthreads) {
+  const int n_step_words = p.nsteps * (int)(sizeof(PeelStep) / 4);
+  const int32_t* steps = reinterpret_cast<const int32_t*>(p.steps);
+  for (int i = threadIdx.x; i < n_step_words; i += nthreads) prog[i] = steps[i];
+  for (int i = threadIdx.x; i < p.nsubs; i += nthreads) prog[n_step_words + i] = p.subs[i];
+  __syncthreads();
+}
+
 // ------------------------------------------------------------- scalar form --
 template <int THREADS>
-__device__ __forceinline__ void peel_block(const PeelParams& p, int64_t block, float* xs) {
+__device__ __forceinline__ void peel_block(const PeelParams& p, int64_t block, float* xs,
+                                           const PeelStep* steps, const int32_t* subs) {
   const int tid = threadIdx.x;
   const int64_t total = p.Mb * p.N;
   const int64_t e = block * THREADS + tid;
@@ -48,7 +62,7 @@ __device__ __forceinline__ void peel_block(const PeelParams& p, int64_t block, f
       y[i] = 0.f;
       const int st = st0 + i;
       if (st < p.nsteps && active) {
-        const PeelStep S = p.steps[st];
+        const PeelStep S = steps[st];
         const int64_t base = (int64_t)S.s * p.Mb;
         if (r < valid_rows(p, base)) {
           if (S.src >= 0)
@@ -62,12 +76,12 @@ __device__ __forceinline__ void peel_block(const PeelParams& p, int64_t block, f
     for (int i = 0; i < kBatch; ++i) {
       const int st = st0 + i;
       if (st >= p.nsteps) break;
-      const PeelStep S = p.steps[st];
+      const PeelStep S = steps[st];
       const int64_t base = (int64_t)S.s * p.Mb;
       const int64_t valid = valid_rows(p, base);
       float x = 0.f;
       if (r < valid) {
-        const int32_t* sub = p.subs + S.sub_off;
+        const int32_t* sub = subs + S.sub_off;
         if (S.f64) {
           double acc = (double)y[i];
           for (int u = 0; u < S.nsub; ++u) acc -= (double)xs[sub[u] * THREADS + tid];
@@ -91,7 +105,8 @@ __device__ __forceinline__ void peel_block(const PeelParams& p, int64_t block, f
 
 // ------------------------------------------------------------- vector form --
 template <int THREADS>
-__device__ __forceinline__ void peel_block4(const PeelParams& p, int64_t block, v4f* xs) {
+__device__ __forceinline__ void peel_block4(const PeelParams& p, int64_t block, v4f* xs,
+                                            const PeelStep* steps, const int32_t* subs) {
   const int tid = threadIdx.x;
   const int64_t n4 = p.N / 4;
   const int64_t total4 = p.Mb * n4;
@@ -108,7 +123,7 @@ __device__ __forceinline__ void peel_block4(const PeelParams& p, int64_t block, 
       y[i] = v4f{0.f, 0.f, 0.f, 0.f};
       const int st = st0 + i;
       if (st < p.nsteps && active) {
-        const PeelStep S = p.steps[st];
+        const PeelStep S = steps[st];
         const int64_t base = (int64_t)S.s * p.Mb;
         if (r < valid_rows(p, base)) {
           if (S.src >= 0)
@@ -122,12 +137,12 @@ __device__ __forceinline__ void peel_block4(const PeelParams& p, int64_t block, 
     for (int i = 0; i < kBatch; ++i) {
       const int st = st0 + i;
       if (st >= p.nsteps) break;
-      const PeelStep S = p.steps[st];
+      const PeelStep S = steps[st];
       const int64_t base = (int64_t)S.s * p.Mb;
       const int64_t valid = valid_rows(p, base);
       v4f x = {0.f, 0.f, 0.f, 0.f};
       if (r < valid) {
-        const int32_t* sub = p.subs + S.sub_off;
+        const int32_t* sub = subs + S.sub_off;
         if (S.f64) {
           v4d acc = {(double)y[i][0], (double)y[i][1], (double)y[i][2], (double)y[i][3]};
           for (int u = 0; u < S.nsub; ++u) {
@@ -155,40 +170,40 @@ __device__ __forceinline__ void peel_block4(const PeelParams& p, int64_t block, 
 
 template <int THREADS>
 __global__ __launch_bounds__(THREADS) void peel_kernel(PeelParams p) {
-  extern __shared__ float xs[];  // [nslots][THREADS]
-  peel_block<THREADS>(p, blockIdx.x, xs);
+  extern __shared__ float xs[];  // [nslots][THREADS], then the program
+  int32_t* prog = reinterpret_cast<int32_t*>(xs + (size_t)p.nslots * THREADS);
+  stage_program(p, prog, THREADS);
+  peel_block<THREADS>(p, blockIdx.x, xs, reinterpret_cast<const PeelStep*>(prog),
+                      prog + p.nsteps * (int)(sizeof(PeelStep) / 4));
 }
 
-template <int THREADS>
-__global__ __launch_bounds__(THREADS) void peel4_kernel(PeelParams p) {
-  extern __shared__ v4f xs4[];  // [nslots][THREADS]
-  peel_block4<THREADS>(p, blockIdx.x, xs4);
-}
-
-// Grouped peel: blocks [pstart[i], pstart[i+1]) run product i's program
-// (vector form: grouped products have N a multiple of 4).
+// Grouped peel: block b runs product pmap[b]'s program (vector form:
+// grouped products have N a multiple of 4).
 __global__ __launch_bounds__(128) void peel_grouped_kernel(const GroupDesc* d,
-                                                           const int64_t* pstart, int32_t count) {
-  extern __shared__ v4f xs4[];
+                                                           const int64_t* pstart,
+                                                           const int32_t* pmap,
+                                                           int32_t max_slots) {
+  extern __shared__ v4f xs4[];  // [max_slots][128], then the product's program
   const int64_t b = blockIdx.x;
-  int lo = 0, hi = count - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) / 2;
-    if (pstart[mid] <= b) lo = mid; else hi = mid - 1;
-  }
-  peel_block4<128>(d[lo].pe, b - pstart[lo], xs4);
+  const int prod = pmap[b];
+  const PeelParams& p = d[prod].pe;
+  int32_t* prog = reinterpret_cast<int32_t*>(xs4 + (size_t)max_slots * 128);
+  stage_program(p, prog, 128);
+  peel_block4<128>(p, b - pstart[prod], xs4, reinterpret_cast<const PeelStep*>(prog),
+                   prog + p.nsteps * (int)(sizeof(PeelStep) / 4));
 }
 
 }  // namespace
 
-hipError_t launch_peel_grouped(const GroupDesc* d, const int64_t* pstart, int32_t count,
-                               int64_t total_blocks, int32_t max_slots, hipStream_t stream) {
+hipError_t launch_peel_grouped(const GroupDesc* d, const int64_t* pstart, const int32_t* pmap,
+                               int64_t total_blocks, int32_t max_slots, size_t max_program,
+                               hipStream_t stream) {
   if (total_blocks == 0) return hipSuccess;
-  const size_t lds = (size_t)max_slots * 128 * 16;
+  const size_t lds = (size_t)max_slots * 128 * 16 + max_program;
   if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
   if (total_blocks > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL(peel_grouped_kernel, dim3((unsigned)total_blocks), dim3(128), lds, stream,
-                     d, pstart, count);
+                     d, pstart, pmap, max_slots);
   return hipGetLastError();
 }
 
@@ -200,7 +215,8 @@ hipError_t launch_peel(const PeelParams& p, hipStream_t stream) {
   const int64_t total = p.Mb * p.N;
   int threads = 256;
   if ((int64_t)p.nslots * 256 * 4 > 64 * 1024) threads = 64;
-  const size_t lds = (size_t)p.nslots * threads * sizeof(float);
+  const size_t lds =
+      (size_t)p.nslots * threads * sizeof(float) + peel_program_bytes(p.nsteps, p.nsubs);
   if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
   const int64_t blocks = (total + threads - 1) / threads;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
