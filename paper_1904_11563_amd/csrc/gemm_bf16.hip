@@ -13,8 +13,9 @@
 // MFMA operands: lane (q = lane/16, c = lane%16) supplies row c of A and
 // column c of B, eight consecutive k values each (k = 8q .. 8q+7 of the
 // step); the same k assignment on both sides makes the contraction exact
-// whatever order the unit sums in.  Output columns are interleaved as in
-// the FP32 kernel (subtile j, column c -> 4c + j) for float4 stores.
+// whatever order the unit sums in.  In the per-symbol tiles output columns
+// are interleaved as in the FP32 kernel (subtile j, column c -> 4c + j) for
+// float4 stores; the flat tiles below keep them in order.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -301,12 +302,21 @@ __device__ __forceinline__ void bf16_tile(const GemmParams& p, int si, int mt, i
 // rows of the two A rows it stages; the encode sums the members in FP32 and
 // splits the sum into BF16 hi / lo while staging.  8 waves (2 x 4) of
 // 64 x 64, K-stages of 32, the next stage's loads in registers during the
-// current stage's MFMAs, LDS double buffer.  Rows past a product's end and B rows past N come back as zeros
-// from the buffer resources' range check.  Needs K a multiple of 32.
+// current stage's MFMAs, LDS double buffer.  Rows past a product's end and B
+// rows past N come back as zeros from the buffer resources' range check.
+// Needs K a multiple of 32.  Output columns are not interleaved here (B is
+// stored n-major, and interleaved columns would read rows four apart, which
+// no row swizzle spreads over the banks).
 namespace flat {
 constexpr int BM = 128, BN = 256, NT = 512;
 constexpr int TM = 64, TN = 64, FM = 4, FN = 4;  // wave tile (2 x 4 waves)
-constexpr int A_PLANE = BM * KS, B_PLANE = BN * KS;
+constexpr int FKS = BK;  // LDS row: 32 bf16 = four 16-byte granules, no padding
+// Granule g of row r sits in slot g ^ ((r >> 2) & 3): the 16 rows read by a
+// k group and the 4 rows written per 256 bytes then cover all 64 banks.
+__device__ __forceinline__ int swz(int row, int granule) {
+  return row * FKS + ((granule ^ ((row >> 2) & 3)) << 3);
+}
+constexpr int A_PLANE = BM * FKS, B_PLANE = BN * FKS;
 constexpr int UA = BM * BK / 4 / NT;        // float4 of A per thread per member (2)
 constexpr int UB = BN * BK * 2 / 16 / NT;   // 16-byte B chunks per thread per plane (2)
 constexpr int kRsrcWord3 = 0x00020000;      // gfx9 raw buffer, 32-bit elements
@@ -406,10 +416,9 @@ __device__ __forceinline__ void bf16_flat_tile(const GemmParams& p, int mt, int 
         if (row < M) sum += *reinterpret_cast<const v4f*>(p.A + row * lda + k0 + ak);
       }
       const v4bf hi = to_bf16(sum);
-      *reinterpret_cast<v4bf*>(st + (ar + 64 * u) * KS + ak) = hi;
-      if (SPLIT == 3)
-        *reinterpret_cast<v4bf*>(st + A_PLANE + (ar + 64 * u) * KS + ak) =
-            to_bf16(sum - from_bf16(hi));
+      const int ao = swz(ar + 64 * u, ak >> 3) + (ak & 7);
+      *reinterpret_cast<v4bf*>(st + ao) = hi;
+      if (SPLIT == 3) *reinterpret_cast<v4bf*>(st + A_PLANE + ao) = to_bf16(sum - from_bf16(hi));
     }
     us* Bs = st + NPL * A_PLANE;
 #pragma unroll
@@ -417,7 +426,7 @@ __device__ __forceinline__ void bf16_flat_tile(const GemmParams& p, int mt, int 
 #pragma unroll
       for (int c = 0; c < UB; ++c) {
         const int f = tid + NT * c;
-        *reinterpret_cast<v4u*>(Bs + pl * B_PLANE + (f >> 2) * KS + (f & 3) * 8) = bre[pl][c];
+        *reinterpret_cast<v4u*>(Bs + pl * B_PLANE + swz(f >> 2, f & 3)) = bre[pl][c];
       }
   };
 
@@ -434,16 +443,18 @@ __device__ __forceinline__ void bf16_flat_tile(const GemmParams& p, int mt, int 
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
       const int r = wm * TM + i * 16 + c16;
-      ah[i] = *reinterpret_cast<const v8bf*>(st + r * KS + 8 * q);
-      if (SPLIT == 3) al[i] = *reinterpret_cast<const v8bf*>(st + A_PLANE + r * KS + 8 * q);
+      ah[i] = *reinterpret_cast<const v8bf*>(st + swz(r, q));
+      if (SPLIT == 3) al[i] = *reinterpret_cast<const v8bf*>(st + A_PLANE + swz(r, q));
     }
-    // one output column group at a time keeps two B fragments live
+    // one output column group at a time keeps two B fragments live; MFMA
+    // column c16 of subtile j is output column 16 j + c16, so the 16 lanes
+    // of a k group read 16 consecutive B rows
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
-      const int n = wn * TN + 4 * c16 + j;  // interleaved output columns
-      const v8bf bh = *reinterpret_cast<const v8bf*>(Bs + n * KS + 8 * q);
+      const int n = wn * TN + 16 * j + c16;
+      const v8bf bh = *reinterpret_cast<const v8bf*>(Bs + swz(n, q));
       if (SPLIT == 3) {
-        const v8bf bl = *reinterpret_cast<const v8bf*>(Bs + B_PLANE + n * KS + 8 * q);
+        const v8bf bl = *reinterpret_cast<const v8bf*>(Bs + B_PLANE + swz(n, q));
 #pragma unroll
         for (int i = 0; i < FM; ++i) {
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
@@ -468,8 +479,8 @@ __device__ __forceinline__ void bf16_flat_tile(const GemmParams& p, int mt, int 
     __syncthreads();
   }
 
-  const bool vec_ok = (p.ldc & 3) == 0 && (N & 3) == 0;
-  const int64_t col = n0 + wn * TN + 4 * c16;
+  // epilogue: lane holds rows 4q .. 4q+3 of column 16 j + c16 of each subtile
+  const int64_t col0 = n0 + wn * TN + c16;
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -480,22 +491,16 @@ __device__ __forceinline__ void bf16_flat_tile(const GemmParams& p, int mt, int 
       const int64_t lr = gr - si * Mb;
       const int dest = p.syms[4 * si + 2];
       float* dst;
-      bool vec = vec_ok;
       if (dest >= 0) {
-        dst = p.Y + ((int64_t)dest * Mb + lr) * N + col;
+        dst = p.Y + ((int64_t)dest * Mb + lr) * N + col0;
       } else {
         const int64_t row = (-1 - (int64_t)dest) * Mb + lr;
         if (row >= M) continue;
-        dst = p.C + row * p.ldc + col;
+        dst = p.C + row * p.ldc + col0;
       }
-      const v4f v = {acc[i][0][r], acc[i][1][r], acc[i][2][r], acc[i][3][r]};
-      if (col + 3 < N && vec) {
-        *reinterpret_cast<v4f*>(dst) = v;
-      } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (col + e < N) dst[e] = v[e];
-      }
+      for (int j = 0; j < FN; ++j)
+        if (col0 + 16 * j < N) dst[16 * j] = acc[i][j][r];
     }
 }
 
@@ -512,7 +517,10 @@ template <int SPLIT>
 __global__ __launch_bounds__(flat::NT, 1) void gemm_bf16_flat_grouped_kernel(
     const GroupDesc* d, const GroupTile* tiles, int32_t n_tiles) {
   __shared__ __attribute__((aligned(16))) us lds[flat::lds_elems<SPLIT>()];
-  for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+  // Each XCD takes a contiguous run of every grid-sized slice of the list,
+  // so the tiles of one product (adjacent in the list) share an L2.
+  const int slot = xcd_remap(blockIdx.x, gridDim.x);
+  for (int t = slot; t < n_tiles; t += gridDim.x) {
     const GroupTile gt = tiles[t];
     const GemmParams& p = d[gt.prod].g;
     const int mt = gt.lin / p.tiles_n;
