@@ -186,7 +186,10 @@ bpx_status bpx_plan_workspace_bytes(const bpx_plan* plan, size_t* ws_bytes,
 /* Byte offsets of the parts of the plan's workspace (n entries written,
  * at most 7), every part 256-byte aligned; a part the precision does not
  * use has size 0 (its offset equals the next one); entry 6 is the total.
- *   F32:     [0] Y slots
+ *   F32:     [0] Y slots, [1] split-K partial tiles: when Mb and N are
+ *            multiples of 256, K of 32 and M of Mb, room for min(256, 4 T)
+ *            FP32 tiles of 256 x 256 (T = computed symbols x Mb/256 x N/256),
+ *            used by the last round of the 256 x 256 tiling
  *   BF16*:   [0] Y, [1] Bt_hi, [2] Bt_lo: B rounded to bf16 (RNE) and the
  *            bf16 residual, transposed (N x Kp, k contiguous, Kp = K rounded
  *            up to 32, zero past K)
@@ -290,8 +293,10 @@ bpx_status bpx_coded_matmul_grouped(bpx_plan* const* plans, const float* const* 
  * with 2x2, 2x4 and 4x2 waves (the default), used when Mb and N are
  * multiples of 256, K of 32 and every data block is full, otherwise the call
  * takes shape 1; a last round of 256x256 tiles under 90% of the CUs runs as
- * 64x128 sub-tiles.  Every FP32 shape sums in the same order, so the shape
- * never changes a result.  FP8 / FP8x2: shape 0 is one 128x128 tile grid per
+ * pieces of its K range (up to 4, summed in piece order by a second kernel)
+ * when the workspace holds the partial tiles, else as 64x128 sub-tiles.
+ * Results are deterministic; shapes and the split change only the FP32
+ * summation order.  FP8 / FP8x2: shape 0 is one 128x128 tile grid per
  * symbol, shape 1 (the default) one grid of 128x256 tiles over all symbols'
  * codes, used when N rounded up to 128 is a multiple of 256, otherwise
  * shape 0. */

@@ -153,6 +153,12 @@ bpx_status gemm_impl(bpx_plan* plan, const float* A, int64_t lda, const float* B
   p.n_sym = (int32_t)plan->computed.size();
   p.prec = plan->prec;
   p.group_m = g_group_m;
+  if (plan->part_bytes() > 0) {  // FP32 split-K partial tiles of the 256 x 256 tiling
+    size_t off[7];
+    plan->layout(off);
+    p.part = reinterpret_cast<float*>(static_cast<char*>(ws) + off[1]);
+    p.part_tiles = (int32_t)(plan->part_bytes() / (256 * 256 * sizeof(float)));
+  }
   // The GEMM kernels index A rows of a block and B rows of a K-slice with
   // 32-bit offsets.
   if ((plan->Mb + 256) * lda >= ((int64_t)1 << 30) || 64 * ldb + plan->N >= ((int64_t)1 << 30))

@@ -17,6 +17,7 @@
 // owns four adjacent output columns (one float4 store per row).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -384,7 +385,16 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void coded_gemm_f32_wide_kernel(Ge
   const int wm = wave / WN, wn = wave % WN;
   const int q = lane >> 4, c16 = lane & 15;
 
-  const int lin = xcd_remap(blockIdx.x, gridDim.x);
+  const int nk_all = (int)(p.K / BK);
+  int lin, kt0 = 0, kt1 = nk_all;
+  if (p.wide_split) {  // piece b % P of tile wide_lin0 + b / P
+    const int P = p.wide_split, piece = (int)blockIdx.x % P;
+    lin = p.wide_lin0 + (int)blockIdx.x / P;
+    kt0 = piece * nk_all / P;
+    kt1 = (piece + 1) * nk_all / P;
+  } else {
+    lin = xcd_remap(blockIdx.x, gridDim.x);
+  }
   int rp, nt;
   tile_coords(lin, p.n_sym * p.tiles_m, p.tiles_n, p.group_m, &rp, &nt);
   const int si = rp / p.tiles_m;
@@ -475,15 +485,14 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void coded_gemm_f32_wide_kernel(Ge
                                                            acc[i][j], 0, 0, 0);
   };
 
-  const int nk = (int)(p.K / BK);
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    load_half(h, 0);
-    store_half(h, 0, 0);
+    load_half(h, kt0 * BK);
+    store_half(h, 0, kt0 * BK);
   }
   __syncthreads();
-  for (int kt = 0; kt + 1 < nk; ++kt) {
-    const int buf = kt & 1;
+  for (int kt = kt0; kt + 1 < kt1; ++kt) {
+    const int buf = (kt - kt0) & 1;
     const int kn = (kt + 1) * BK;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -494,14 +503,20 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void coded_gemm_f32_wide_kernel(Ge
     __syncthreads();
   }
   {
-    const int buf = (nk - 1) & 1;
+    const int buf = (kt1 - 1 - kt0) & 1;
 #pragma unroll
     for (int h = 0; h < 2; ++h) compute_chunk(As0 + buf * A_SIZE, Bs0 + buf * B_SIZE, h * 16);
   }
 
   float* out;
   int64_t ldo;
-  if (dest >= 0) {
+  int64_t r0 = m0, c0 = n0;  // tile origin in out
+  if (p.wide_split) {        // partial tile, 256 x 256 row-major
+    out = p.part + (int64_t)blockIdx.x * BM * BN;
+    ldo = BN;
+    r0 = 0;
+    c0 = 0;
+  } else if (dest >= 0) {
     out = p.Y + (int64_t)dest * p.Mb * p.N;
     ldo = p.N;
   } else {
@@ -510,17 +525,38 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void coded_gemm_f32_wide_kernel(Ge
   }
 #pragma unroll
   for (int jg = 0; jg < FN / 4; ++jg) {
-    const int64_t col = n0 + wn * TN + jg * 64 + 4 * c16;
+    const int64_t col = c0 + wn * TN + jg * 64 + 4 * c16;
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = m0 + wm * TM + i * 16 + 4 * q + r;
+        const int64_t row = r0 + wm * TM + i * 16 + 4 * q + r;
         const v4f v = {acc[i][4 * jg + 0][r], acc[i][4 * jg + 1][r], acc[i][4 * jg + 2][r],
                        acc[i][4 * jg + 3][r]};
         *reinterpret_cast<v4f*>(out + row * ldo + col) = v;
       }
   }
+}
+
+// Sums the P partial tiles of each split tile in piece order (fixed, so
+// results do not depend on scheduling) and writes the tile's output.
+// grid: tiles x 64 blocks of 256 threads, one float4 per thread.
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmParams p) {
+  const int t = blockIdx.x >> 6;
+  const int e = ((blockIdx.x & 63) << 8) + threadIdx.x;  // float4 index in the tile
+  const int row = e >> 6, col = (e & 63) * 4;
+  const int P = p.wide_split;
+  const float* src = p.part + (int64_t)t * P * 65536 + row * 256 + col;
+  v4f sum = *reinterpret_cast<const v4f*>(src);
+  for (int k = 1; k < P; ++k) sum += *reinterpret_cast<const v4f*>(src + (int64_t)k * 65536);
+  int rp, nt;
+  tile_coords(p.wide_lin0 + t, p.n_sym * p.tiles_m, p.tiles_n, p.group_m, &rp, &nt);
+  const int si = rp / p.tiles_m;
+  const int64_t m = (int64_t)(rp - si * p.tiles_m) * 256 + row, n = (int64_t)nt * 256 + col;
+  const int dest = p.syms[4 * si + 2];
+  float* out = dest >= 0 ? p.Y + ((int64_t)dest * p.Mb + m) * p.N + n
+                         : p.C + ((int64_t)(-1 - dest) * p.Mb + m) * p.ldc + n;
+  *reinterpret_cast<v4f*>(out) = sum;
 }
 
 struct TileEntry {
@@ -565,6 +601,7 @@ hipError_t launch_coded_gemm(const GemmParams& p0, int32_t tile, hipStream_t str
   GemmParams p = p0;
   p.wide_rem = 0;
   p.wide_lin0 = 0;
+  p.wide_split = 0;
   if (tile >= kWideTile) {
     // The wide tile has no edge path: shapes with a partial tile, a partial
     // data block or a ragged last K-slice take the 64 x 128 tile.
@@ -590,6 +627,22 @@ hipError_t launch_coded_gemm(const GemmParams& p0, int32_t tile, hipStream_t str
         if (err != hipSuccess) return err;
       }
       if (wide_tiles == T) return hipSuccess;
+      // Last round: split each remaining tile's K range into P pieces (as
+      // many as fill the CUs, at most 4, each at least 8 slices) when the
+      // workspace holds the partial tiles; otherwise 64 x 128 sub-tiles.
+      const int64_t R = T - wide_tiles;
+      int64_t P = std::min<int64_t>(4, S / R);
+      while (P > 1 && (p.K / 32) / P < 8) --P;
+      if (p.part && P >= 2 && R * P <= p.part_tiles) {
+        p.wide_split = (int32_t)P;
+        p.wide_lin0 = (int32_t)wide_tiles;
+        hipLaunchKernelGGL(e.kernel, dim3((unsigned)(R * P)), dim3(e.threads), 0, stream, p);
+        hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
+        hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)(R * 64)), dim3(256), 0, stream,
+                           p);
+        return hipGetLastError();
+      }
       const TileEntry& s = kTiles[1];
       p.wide_rem = 1;
       p.wide_lin0 = (int32_t)wide_tiles;

@@ -78,8 +78,18 @@ struct bpx_plan {
   int64_t r128(int64_t x) const { return (x + 127) / 128 * 128; }
   bool is_fp8() const { return prec == BPX_PREC_FP8 || prec == BPX_PREC_FP8X2; }
   bool is_bf16() const { return prec == BPX_PREC_BF16 || prec == BPX_PREC_BF16X3; }
+  // FP32 plans whose shape takes the 256 x 256 tiling reserve room for the
+  // split-K partial tiles of its last round: at most 4 pieces per tile and
+  // at most 256 partial tiles (one per CU) of 256 x 256 FP32.
+  size_t part_bytes() const {
+    if (prec != BPX_PREC_F32 || Mb % 256 != 0 || N % 256 != 0 || K % 32 != 0 || M % Mb != 0)
+      return 0;
+    const int64_t T = (int64_t)computed.size() * (Mb / 256) * (N / 256);
+    const int64_t tiles = T * 4 < 256 ? T * 4 : 256;
+    return (size_t)tiles * 256 * 256 * sizeof(float);
+  }
   // Offsets in bytes of the workspace parts:
-  //   F32:    [0] Y
+  //   F32:    [0] Y, [1] split-K partial tiles (256 x 256 tiling only)
   //   BF16*:  [0] Y, [1] Bt_hi, [2] Bt_lo (BF16x3)
   //   FP8*:   [0] Y, [1] Aq, [2] Aq2 (FP8x2), [3] sA, [4] Bq, [5] sB
   // Missing parts get the offset of the next part (size 0).  [6] = total.
@@ -107,7 +117,9 @@ struct bpx_plan {
       b += align256((size_t)(r128(K) / 128) * (size_t)(r128(N) / 128) * 4);
       off[6] = b;
     } else {
-      for (int i = 1; i < 7; ++i) off[i] = b;
+      off[1] = b;
+      b += part_bytes();
+      for (int i = 2; i < 7; ++i) off[i] = b;
     }
     off[6] = b;
   }

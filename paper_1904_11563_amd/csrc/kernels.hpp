@@ -34,6 +34,13 @@ struct GemmParams {
   // b % per of 256 x 256 tile wide_lin0 + b / per (per = sub-tiles per tile).
   int32_t wide_rem;
   int32_t wide_lin0;
+  // Split-K mode of the 256 x 256 tiling: when wide_split = P > 0, block b
+  // computes k-slice range (b % P) of tile wide_lin0 + b / P into partial
+  // tile b of part (256 x 256 FP32, row-major); a reduction kernel sums the
+  // P partials of each tile in piece order and writes the tile's output.
+  int32_t wide_split;
+  int32_t part_tiles;  // capacity of part in 256 x 256 tiles (0: no split-K)
+  float* part;
   // BF16 / BF16x3: B split into transposed bf16 planes (N x kp, k contiguous)
   const unsigned short* bt_hi;
   const unsigned short* bt_lo;

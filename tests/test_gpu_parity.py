@@ -296,12 +296,41 @@ def test_fp32_scale_full_size_sampled():
     assert np.isfinite(C).all()
 
 
+def test_wide_tile_split_k_last_round():
+    """The 256 x 256 FP32 tiling on a shape with one full round and a short
+    last round (12 symbols x 24 column tiles = 288 tiles; K = 1024 gives the
+    last 32 tiles four 8-slice pieces each, reduced in piece order): integer
+    operands decode exactly, float operands agree with the 64 x 128 tiling to
+    the FP32 summation-order level, and two runs are bit-identical."""
+    code = code642()
+    M, K, N = 2048, 1024, 6144
+    plan = bpx.Plan(code, list(range(6)), 0, bpx.MODE_FULL, M, K, N)
+    A = inputs.integers(8, inputs.TAG_A, (M, K))
+    B = inputs.integers(8, inputs.TAG_B, (K, N))
+    Af = inputs.normal(8, inputs.TAG_A, (M, K))
+    Bf = inputs.normal(8, inputs.TAG_B, (K, N))
+    try:
+        bpx.force_tile(6)
+        _say("wide split-K integer")
+        C = run(plan, A, B)
+        assert np.array_equal(C.astype(np.float64), A.astype(np.float64) @ B.astype(np.float64))
+        Cw = run(plan, Af, Bf)
+        Cw2 = run(plan, Af, Bf)
+        bpx.force_tile(1)
+        C1 = run(plan, Af, Bf)
+    finally:
+        bpx.force_tile(-1)
+    assert np.array_equal(Cw, Cw2)
+    assert relf(Cw, C1) <= 1e-6
+    assert relf(Cw, Af.astype(np.float64) @ Bf.astype(np.float64)) <= TOL_F32
+
+
 def test_wide_tile_exact_and_identical_to_small_tile():
     """The 256 x 256 FP32 tiles (three wave layouts) on a shape that fills
-    more than one round of the CUs, so that the last round runs as 64 x 128
-    sub-tiles of the wide tiling: integer operands decode to A.B exactly, and
-    float operands give bit-identical results to the 64 x 128 tile (every
-    FP32 tile shape sums in the same order)."""
+    more than one round of the CUs, whose last round (K = 96: too few
+    slices to split) runs as 64 x 128 sub-tiles of the wide tiling: integer
+    operands decode to A.B exactly, and float operands give bit-identical
+    results to the 64 x 128 tile (both sum in the same order)."""
     code = code642()
     M, K, N = 2048, 96, 6144           # Mb = 256; 12 symbols x 24 column tiles
     arrival = list(range(6))

@@ -198,3 +198,15 @@ def test_workspace_bytes():
     # BF16x3 adds two transposed bf16 planes of B (N x K rounded up to 32)
     p3 = bpx.Plan(c, [3, 4, 0, 1, 2], 0, bpx.MODE_FULL, 90, 16, 10, bpx.PREC_BF16X3)
     assert p3.workspace_bytes()[0] == ws + 2 * al(10 * 32 * 2)
+    # FP32 shapes of the 256 x 256 tiling add min(256, 4 T) partial tiles
+    # of 256 x 256 FP32 for the split-K last round (T = symbols x tiles)
+    pw = bpx.Plan(c, [3, 4, 0, 1, 2], 0, bpx.MODE_FULL, 9 * 256, 64, 512)
+    d = pw.schedule()["dest"]
+    y = al(int((d >= 0).sum()) * 256 * 512 * 4)
+    T = len(d) * 1 * 2
+    assert pw.workspace_layout()[1] == y
+    assert pw.workspace_bytes()[0] == y + min(256, 4 * T) * 256 * 256 * 4
+    # ... and shapes outside it (Mb = 250) add nothing
+    pn = bpx.Plan(c, [3, 4, 0, 1, 2], 0, bpx.MODE_FULL, 9 * 250, 64, 512)
+    dn = pn.schedule()["dest"]
+    assert pn.workspace_bytes()[0] == al(int((dn >= 0).sum()) * 250 * 512 * 4)
