@@ -12,8 +12,9 @@ the same operands, the dominant kernel's roofline from HIP events over the
 timed region, and the float64 oracle on the host for a bounded sample.
 
 Other workloads (--workload): fp32_small, bf16_small (split-BF16x3),
-fp8_mojette (FP8x2, Mojette code), batch (256 uneven products, one grouped
-launch sequence captured in a HIP graph).
+fp8_mojette (FP8x2, Mojette Construction A), mojette_b (FP32, Mojette
+Construction B at the headline's shape), batch (256 uneven products, one
+grouped launch sequence captured in a HIP graph).
 
 Prints ONE JSON line.
 """
@@ -40,7 +41,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="fp32_scale",
-                    choices=["fp32_scale", "fp32_small", "bf16_small", "fp8_mojette", "batch"])
+                    choices=["fp32_scale", "fp32_small", "bf16_small", "fp8_mojette", "mojette_b",
+                             "batch"])
     ap.add_argument("--prec", default=None, help="override the workload's precision")
     ap.add_argument("--mode", default="arrival", choices=["arrival", "full", "min"])
     ap.add_argument("--seed", type=int, default=0)
@@ -241,8 +243,9 @@ def run_single(args):
     gemm_flops = 2.0 * Mb * w.K * w.N * n_comp
     achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12
     if Mb % 256 == 0 and w.N % 256 == 0 and w.K % 32 == 0 and w.M % Mb == 0:
-        f32_kernel = ("coded_gemm_f32_wide_kernel<4,2> (full rounds of 256x256 tiles) + "
-                      "coded_gemm_f32_kernel<64,128,32,2> (last round as sub-tiles), one call")
+        f32_kernel = ("coded_gemm_f32_wide_kernel<4,2> (full rounds of 256x256 tiles; a short "
+                      "last round split along K + splitk_reduce_kernel, or as "
+                      "coded_gemm_f32_kernel<64,128,32,2> sub-tiles), one call")
     else:
         f32_kernel = "coded_gemm_f32_kernel<64,128,32,2>"
     kernel = {"f32": f32_kernel, "bf16": "split_b + coded_gemm_bf16_kernel",

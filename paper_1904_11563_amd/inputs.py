@@ -72,6 +72,8 @@ CODE_642 = CodeSpec("search", n=6, k=4, b=2, sigma=3, seed=0, restarts=4, iters=
 CODE_1284 = CodeSpec("search", n=12, k=8, b=4, sigma=4, seed=0, restarts=1, iters=40000)
 CODE_1282 = CodeSpec("search", n=12, k=8, b=2, sigma=4, seed=0, restarts=1, iters=40000)
 CODE_MOJ = CodeSpec("mojette", n=24, k=16, b=8, qe=0)
+# Construction B (q_i = 2^qe, odd p_i): sigma = ceil(k / 2^qe) = 4 at k = 8.
+CODE_MOJ_B = CodeSpec("mojette", n=12, k=8, b=4, qe=1)
 
 
 @dataclass
@@ -94,6 +96,10 @@ WORKLOADS = {
                            "erasure:2"),
     "fp8_mojette": Workload("fp8_mojette", 16384, 16384, 8192, CODE_MOJ, "fp8", "normal",
                             "erasure:8"),
+    # Mojette Construction B at the headline's shape, FP32, a third of the
+    # columns erased
+    "mojette_b": Workload("mojette_b", 8192, 8192, 4096, CODE_MOJ_B, "f32", "normal",
+                          "erasure:4"),
 }
 
 

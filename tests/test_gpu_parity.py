@@ -230,6 +230,35 @@ def test_mojette_codes_integer_exact():
         assert np.array_equal(C.astype(np.float64), A.astype(np.float64) @ B), (k, b, n, qe)
 
 
+def test_construction_b_codes_exact_and_full_size_sampled():
+    """Mojette Construction B (q_i = 2^qe, odd p_i): integer operands decode
+    exactly for several erasure patterns at q_e = 1 and 2, and the
+    8192x8192 . 8192x4096 FP32 workload (k=8, b=4, n=12, q_e=1, 4 columns
+    erased) meets the FP32 bound on sampled rows."""
+    for qe in (1, 2):
+        code = bpx.Code.mojette(8, 4, 12, qe)
+        M, K, N = 32 * 9 + 5, 96, 100
+        A = inputs.integers(40 + qe, inputs.TAG_A, (M, K))
+        B = inputs.integers(40 + qe, inputs.TAG_B, (K, N))
+        R = A.astype(np.float64) @ B.astype(np.float64)
+        for seed in range(4):
+            arrival, lost = inputs.erasure_arrival(seed, 12, 4)
+            plan = bpx.Plan(code, arrival, lost, bpx.MODE_ERASURE, M, K, N)
+            _say("construction B", qe, seed, plan.info())
+            assert plan.decodable
+            assert np.array_equal(run(plan, A, B).astype(np.float64), R), (qe, seed)
+    w = inputs.WORKLOADS["mojette_b"]
+    A, B = inputs.operands(w, seed=0)
+    arrival, lost, _ = inputs.arrival_of(w, seed=0)
+    plan = bpx.Plan(lib_code(w.code), arrival, lost, bpx.MODE_ERASURE, w.M, w.K, w.N)
+    _say("mojette_b plan", plan.info())
+    C = run(plan, A, B)
+    rows = np.concatenate([np.arange(s * 256, s * 256 + 256, 37)[:4] for s in range(32)])
+    e = relf(C[rows], A[rows].astype(np.float64) @ B.astype(np.float64))
+    _say("mojette_b sampled relF", e)
+    assert e <= TOL_F32
+
+
 def test_identity_code_is_plain_gemm():
     code = bpx.Code.identity(4, 2)
     M, K, N = 203, 100, 77
