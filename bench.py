@@ -267,29 +267,34 @@ def run_single(args):
                              "plan_host_us": plan_us, "code_build_s": code_s},
                 "roofline": roofline, "hbm": hbm})
     out.update(refs)
+    out["latency_model"] = latency_model(bpx, code, w, prec, gemm_ms, n_comp, hbm, refs, spec)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_single(A, B, code, arrival, lost, mode, w, args.cpu_seconds)
     return out
 
 
-def peel_bytes(plan, M, N):
-    """Algorithmic (read, write) bytes of a plan's peel: a block whose
-    releaser's product went to a workspace slot is read there and written to
-    C; a block released into C in place is read only if a later release
-    subtracts it."""
-    sch = plan.schedule()
-    Mb = plan.info()["Mb"]
-    rows = lambda s: max(0, min(Mb, M - s * Mb))
-    dest = dict(zip(sch["computed"].tolist(), sch["dest"].tolist()))
-    used = set(sch["sub_data"].tolist())
-    rd = wr = 0
-    for s, g in enumerate(sch["releaser"].tolist()):
-        d = dest[g]
-        if d >= 0 or s in used:
-            rd += rows(s) * N * 4
-        if d >= 0:
-            wr += rows(s) * N * 4
-    return rd, wr
+def latency_model(bpx, code, w, prec, gemm_ms, n_comp, hbm, refs, spec, samples=500):
+    """The paper's T = T_e + min_S max_{i in S} T_i + T_d with exponential
+    task times (rate 1 per unit of work), the unit being the measured GPU
+    time of one coded product and the peel at its measured bandwidth; the
+    uncoded case runs the identity code at the uncoded product's time."""
+    from paper_1904_11563_amd import latency
+    gbps = hbm["peel"]["GBps"]
+    res = {"unit": "us", "mu": 1.0, "model": "column done when its b products are; "
+           "prefix from the library planner; encode fused into the products"}
+    lm = latency.summary(latency.sample(bpx, code, w.M, w.K, w.N, gemm_ms * 1e-3 / n_comp,
+                                        gbps * 1e9 if gbps else None, samples=samples, prec=prec))
+    res["coded"] = {k: (v * 1e6 if k in ("E_T", "encode", "cluster", "decode") else v)
+                    for k, v in lm.items()}
+    if refs.get("uncoded_own_tflops"):
+        kb = spec.k * spec.b
+        t_u = 2.0 * w.M * w.K * w.N / (refs["uncoded_own_tflops"] * 1e12) / kb
+        ident = bpx.Code.identity(spec.k, spec.b)
+        lu = latency.summary(latency.sample(bpx, ident, w.M, w.K, w.N, t_u, None,
+                                            samples=samples, prec=prec))
+        res["uncoded"] = {k: (v * 1e6 if k in ("E_T", "encode", "cluster", "decode") else v)
+                          for k, v in lu.items()}
+    return res
 
 
 def hbm_kernels(torch, bpx, plan, code, Ad, Cd, ws, w, info, steps):
@@ -307,6 +312,7 @@ def hbm_kernels(torch, bpx, plan, code, Ad, Cd, ws, w, info, steps):
     bpx.encode(plan, Ad, out_enc)
     enc_ms = timed(torch, lambda: bpx.encode(plan, Ad, out_enc), steps)
     del out_enc
+    from paper_1904_11563_amd.latency import peel_bytes
     rd, wr = peel_bytes(plan, M, N)
     peel_ms = timed(torch, lambda: bpx.peel_decode(plan, ws, Cd), steps)
     res = {"peak_GBps": 8000.0}
@@ -348,7 +354,7 @@ def run_batch(args):
     import numpy as np
     import torch
 
-    from paper_1904_11563_amd import autotune, bpx, inputs
+    from paper_1904_11563_amd import autotune, bpx, inputs, latency
 
     tuned = autotune.load()
     if args.tile >= 0:
@@ -413,7 +419,7 @@ def run_batch(args):
     for (M, K, N, k), inf, pl in zip(shapes, meta, plans):
         comp_flops += 2.0 * inf["Mb"] * K * N * inf["n_computed"]
         split_bytes += K * N * 4 + N * (-(-K // 32) * 32) * 2 * planes
-        r, wb = peel_bytes(pl, M, N)
+        r, wb = latency.peel_bytes(pl, M, N)
         peel_rd += r
         peel_wr += wb
     hbm = {"peak_GBps": 8000.0}
