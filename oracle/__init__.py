@@ -20,6 +20,9 @@ Hierarchically Distributed Matrix Multiplication", arXiv 1904.11563):
                   symbols, the arrival prefix and the release schedule.
 * ``pipeline``  - encode, coded products, numeric peel and the uncoded
                   product, all in float64.
+* ``pipeline2d``- the two-dimensional form of Examples 1 and 2 (A split by
+                  rows and B by columns, information symbols a_r b_c, gray
+                  symbols), float64.
 
 Parity status of each function is stated in its docstring; every function is
 pinned by a test under ``tests/`` against facts the paper or mathematics fixes.
