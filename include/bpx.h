@@ -155,8 +155,28 @@ bpx_status bpx_plan_create(const bpx_code* code, const int32_t* arrival, int32_t
                            int32_t n_lost, int32_t mode, int64_t M, int64_t K, int64_t N,
                            int32_t prec, bpx_plan** out);
 
-/* Scalar facts of a plan; any pointer may be NULL.  Mb = ceil(M/(k*b)).
- * depth_max = the largest release round. */
+/* The same plan for the paper's two-dimensional form (Sec. III-A, Examples
+ * 1 and 2): with k*b = grid^2, A is split into grid row blocks (Mb =
+ * ceil(M/grid) rows) and B into grid column blocks (Nb = N/grid columns), and
+ * data id s = r*grid + c is the block product A_r B_c, whose result fills C
+ * rows r*Mb .., columns c*Nb ...  A coded symbol whose members share a B
+ * block is computed as (sum of A blocks) . B_c, one whose members share an A
+ * block as A_r . (sum of B blocks), and any other (the paper's gray cells)
+ * as the sum of its members' block products (a K-concatenated product).
+ * FP32 only; needs K % 4 == 0 and N a multiple of 4*grid
+ * (BPX_E_UNSUPPORTED otherwise), k*b a perfect square >= 4 (BPX_E_INVALID).
+ * Prefix, schedule and error behaviour as bpx_plan_create; Y slots are
+ * Mb x Nb.  bpx_encode and grouped launches do not take such plans. */
+bpx_status bpx_plan_create2d(const bpx_code* code, const int32_t* arrival, int32_t n_arrival,
+                             int32_t n_lost, int32_t mode, int64_t M, int64_t K, int64_t N,
+                             int32_t prec, bpx_plan** out);
+
+/* Block grid of a plan: grid = 1 and Nb = N for row-block plans. */
+bpx_status bpx_plan_grid(const bpx_plan* plan, int32_t* grid, int64_t* Nb);
+
+/* Scalar facts of a plan; any pointer may be NULL.  Mb = ceil(M/(k*b))
+ * (two-dimensional plans: ceil(M/grid)).  depth_max = the largest release
+ * round. */
 bpx_status bpx_plan_info(const bpx_plan* plan, int32_t* decodable, int32_t* prefix_m,
                          int32_t* n_computed, int32_t* depth_max, int32_t* n_unrecovered,
                          int64_t* Mb);

@@ -41,7 +41,8 @@ MODE_NAMES = {"erasure": MODE_ERASURE, "straggler": MODE_STRAGGLER,
 
 EXPORTS = [
     "bpx_code_build", "bpx_code_from_csr", "bpx_code_info", "bpx_code_csr", "bpx_code_free",
-    "bpx_plan_create", "bpx_plan_info", "bpx_plan_schedule", "bpx_plan_workspace_bytes",
+    "bpx_plan_create", "bpx_plan_create2d", "bpx_plan_grid", "bpx_plan_info",
+    "bpx_plan_schedule", "bpx_plan_workspace_bytes",
     "bpx_plan_workspace_layout",
     "bpx_plan_upload", "bpx_plan_free", "bpx_encode", "bpx_coded_gemm", "bpx_peel_decode",
     "bpx_coded_matmul", "bpx_coded_matmul_grouped", "bpx_group_workspace_bytes",
@@ -70,6 +71,9 @@ _sig = {
     "bpx_code_free": (None, [_p]),
     "bpx_plan_create": (C.c_int, [_p, _i32p, C.c_int32, C.c_int32, C.c_int32, C.c_int64,
                                   C.c_int64, C.c_int64, C.c_int32, C.POINTER(_p)]),
+    "bpx_plan_create2d": (C.c_int, [_p, _i32p, C.c_int32, C.c_int32, C.c_int32, C.c_int64,
+                                    C.c_int64, C.c_int64, C.c_int32, C.POINTER(_p)]),
+    "bpx_plan_grid": (C.c_int, [_p, _i32p, C.POINTER(C.c_int64)]),
     "bpx_plan_info": (C.c_int, [_p] + [_i32p] * 5 + [C.POINTER(C.c_int64)]),
     "bpx_plan_schedule": (C.c_int, [_p] + [C.POINTER(_i32p)] * 5 + [C.POINTER(_u16p),
                                                                     C.POINTER(_i32p)]),
@@ -212,12 +216,14 @@ class Code:
 class Plan:
     """A library-owned plan handle (prefix, schedule, device tables)."""
 
-    def __init__(self, code: Code, arrival, n_lost, mode, M, K, N, prec=PREC_F32):
+    def __init__(self, code: Code, arrival, n_lost, mode, M, K, N, prec=PREC_F32,
+                 two_d=False):
         arr = np.ascontiguousarray(arrival, dtype=np.int32)
         self.code = code
         h = _p()
-        st = _lib.bpx_plan_create(code._h, arr.ctypes.data_as(_i32p), len(arr), n_lost, mode,
-                                  M, K, N, prec, C.byref(h))
+        create = _lib.bpx_plan_create2d if two_d else _lib.bpx_plan_create
+        st = create(code._h, arr.ctypes.data_as(_i32p), len(arr), n_lost, mode,
+                    M, K, N, prec, C.byref(h))
         _check(st, allow=(E_UNDECODABLE,))
         self._h = h
         self.M, self.K, self.N, self.prec, self.mode = M, K, N, prec, mode
@@ -235,6 +241,13 @@ class Plan:
     @property
     def decodable(self):
         return self.info()["decodable"]
+
+    def grid(self):
+        """(grid, Nb): 1 and N for row-block plans."""
+        g = C.c_int32()
+        nb = C.c_int64()
+        _check(_lib.bpx_plan_grid(self._h, C.byref(g), C.byref(nb)))
+        return g.value, nb.value
 
     def schedule(self):
         inf = self.info()

@@ -165,7 +165,13 @@ bpx_status gemm_impl(bpx_plan* plan, const float* A, int64_t lda, const float* B
     return fail(BPX_E_UNSUPPORTED, "block too large for 32-bit tile offsets");
   const int32_t tile = choose_tile(plan->prec, plan->Mb, plan->N, plan->K);
   hipError_t e;
-  if (plan->is_fp8()) {
+  if (plan->grid > 1) {
+    p.grid = plan->grid;
+    p.Nb = plan->Nb;
+    e = launch_coded_gemm_2d(p, stream);
+    if (e == hipErrorInvalidValue)
+      return fail(BPX_E_UNSUPPORTED, "block too large for 32-bit buffer offsets");
+  } else if (plan->is_fp8()) {
     size_t off[7];
     plan->layout(off);
     char* w = static_cast<char*>(ws);
@@ -232,6 +238,8 @@ bpx_status peel_impl(bpx_plan* plan, const void* ws, size_t ws_bytes, float* C, 
   p.nsteps = (int32_t)plan->steps.size();
   p.nslots = plan->n_lds_slots;
   p.nsubs = (int32_t)plan->step_subs.size();
+  p.grid = plan->grid;
+  p.Nb = plan->Nb;
   hipError_t e = launch_peel(p, stream);
   if (e == hipErrorInvalidConfiguration)
     return fail(BPX_E_UNSUPPORTED, "peel needs more LDS than a workgroup has");
@@ -289,6 +297,8 @@ bpx_status group_build(bpx_plan* const* plans, const float* const* A, const floa
     if (!pl) return fail(BPX_E_INVALID, "null plan");
     if (!pl->decodable) return fail(BPX_E_UNDECODABLE, "a plan of the group is not decodable");
     if (pl->prec != prec) return fail(BPX_E_INVALID, "plans of a group must share a precision");
+    if (pl->grid != 1)
+      return fail(BPX_E_UNSUPPORTED, "grouped launch runs row-block (one-dimensional) plans");
     if (pl->K % 4 != 0 || pl->N % 4 != 0)
       return fail(BPX_E_INVALID, "grouped products need K and N multiples of 4");
     if (!A[i] || !B[i] || !C[i] || !aligned16(A[i]) || !aligned16(B[i]) || !aligned16(C[i]))
@@ -365,6 +375,8 @@ bpx_status group_build(bpx_plan* const* plans, const float* const* A, const floa
     pe.nsteps = (int32_t)pl->steps.size();
     pe.nslots = pl->n_lds_slots;
     pe.nsubs = (int32_t)pl->step_subs.size();
+    pe.grid = 1;
+    pe.Nb = pl->N;
     max_program = std::max(max_program, peel_program_bytes(pe.nsteps, pe.nsubs));
     max_slots = std::max(max_slots, pl->n_lds_slots);
     d.b_tn = (int32_t)((pl->N + 63) / 64);
@@ -554,13 +566,47 @@ bpx_status bpx_plan_create(const bpx_code* code, const int32_t* arrival, int32_t
   bpx_plan* p = new (std::nothrow) bpx_plan();
   if (!p) return fail(BPX_E_NOMEM, "out of host memory");
   std::string err;
-  int st = make_plan(*code, arrival, n_arrival, n_lost, mode, M, K, N, prec, p, &err);
+  int st = make_plan(*code, arrival, n_arrival, n_lost, mode, M, K, N, prec, 1, p, &err);
   if (st == BPX_E_INVALID) {
     delete p;
     return fail(BPX_E_INVALID, err);
   }
   *out = p;
   if (st == BPX_E_UNDECODABLE) return fail(BPX_E_UNDECODABLE, "available columns do not peel");
+  return BPX_OK;
+}
+
+bpx_status bpx_plan_create2d(const bpx_code* code, const int32_t* arrival, int32_t n_arrival,
+                             int32_t n_lost, int32_t mode, int64_t M, int64_t K, int64_t N,
+                             int32_t prec, bpx_plan** out) {
+  if (!code || !out) return fail(BPX_E_INVALID, "null argument");
+  *out = nullptr;
+  const int32_t kb = code->kb();
+  int32_t m = 1;
+  while ((int64_t)(m + 1) * (m + 1) <= kb) ++m;
+  if ((int64_t)m * m != kb || m < 2)
+    return fail(BPX_E_INVALID, "the two-dimensional form needs k*b a square of at least 4");
+  if (prec != BPX_PREC_F32) return fail(BPX_E_UNSUPPORTED, "the two-dimensional form runs FP32");
+  if (K % 4 != 0 || N % m != 0 || (N / m) % 4 != 0)
+    return fail(BPX_E_UNSUPPORTED, "the two-dimensional form needs K % 4 == 0 and N / grid a "
+                                   "multiple of 4");
+  bpx_plan* p = new (std::nothrow) bpx_plan();
+  if (!p) return fail(BPX_E_NOMEM, "out of host memory");
+  std::string err;
+  int st = make_plan(*code, arrival, n_arrival, n_lost, mode, M, K, N, prec, m, p, &err);
+  if (st == BPX_E_INVALID) {
+    delete p;
+    return fail(BPX_E_INVALID, err);
+  }
+  *out = p;
+  if (st == BPX_E_UNDECODABLE) return fail(BPX_E_UNDECODABLE, "available columns do not peel");
+  return BPX_OK;
+}
+
+bpx_status bpx_plan_grid(const bpx_plan* plan, int32_t* grid, int64_t* Nb) {
+  if (!plan) return fail(BPX_E_INVALID, "null plan");
+  if (grid) *grid = plan->grid;
+  if (Nb) *Nb = plan->Nb;
   return BPX_OK;
 }
 
@@ -625,6 +671,8 @@ bpx_status bpx_encode(bpx_plan* plan, const float* A, int64_t lda, float* coded_
   bpx_status st = check_device_call(plan);
   if (st != BPX_OK) return st;
   if ((st = check_matrix(A, lda, plan->K, "A")) != BPX_OK) return st;
+  if (plan->grid > 1)
+    return fail(BPX_E_UNSUPPORTED, "stand-alone encode is for row-block plans");
   if (!coded_out || !aligned16(coded_out))
     return fail(BPX_E_INVALID, "coded_out null or misaligned");
   EncodeParams p{};

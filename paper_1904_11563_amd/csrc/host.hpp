@@ -38,6 +38,11 @@ struct bpx_plan {
   bpx_code code;
   int32_t mode = 0, prec = 0;
   int64_t M = 0, K = 0, N = 0, Mb = 0;
+  // Two-dimensional form: data block s = r * grid + c is A row block r times
+  // B column block c (Mb rows, Nb columns); grid = 1 is the row-block form
+  // (Nb = N).
+  int32_t grid = 1;
+  int64_t Nb = 0;
 
   bool decodable = false;
   int32_t prefix_m = 0;
@@ -68,7 +73,7 @@ struct bpx_plan {
   const PeelStep* d_steps = nullptr;
   const int32_t* d_step_subs = nullptr;
 
-  size_t y_bytes() const { return (size_t)n_yslots * (size_t)Mb * (size_t)N * sizeof(float); }
+  size_t y_bytes() const { return (size_t)n_yslots * (size_t)Mb * (size_t)Nb * sizeof(float); }
   // K rounded up to the BF16 kernels' 32-wide k step
   int64_t kp() const { return (K + 31) / 32 * 32; }
   static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
@@ -82,7 +87,8 @@ struct bpx_plan {
   // split-K partial tiles of its last round: at most 4 pieces per tile and
   // at most 256 partial tiles (one per CU) of 256 x 256 FP32.
   size_t part_bytes() const {
-    if (prec != BPX_PREC_F32 || Mb % 256 != 0 || N % 256 != 0 || K % 32 != 0 || M % Mb != 0)
+    if (grid != 1 || prec != BPX_PREC_F32 || Mb % 256 != 0 || N % 256 != 0 || K % 32 != 0 ||
+        M % Mb != 0)
       return 0;
     const int64_t T = (int64_t)computed.size() * (Mb / 256) * (N / 256);
     const int64_t tiles = T * 4 < 256 ? T * 4 : 256;
@@ -162,9 +168,10 @@ struct PeelResult {
 };
 // Round-based peel over the given symbols (ids into code), canonical releaser.
 PeelResult peel(const bpx_code& code, const std::vector<int32_t>& syms);
+// grid = 1: row blocks of A; grid = m > 1: the two-dimensional form (k*b = m^2).
 int make_plan(const bpx_code& code, const int32_t* arrival, int32_t n_arrival, int32_t n_lost,
-              int32_t mode, int64_t M, int64_t K, int64_t N, int32_t prec, bpx_plan* plan,
-              std::string* err);
+              int32_t mode, int64_t M, int64_t K, int64_t N, int32_t prec, int32_t grid,
+              bpx_plan* plan, std::string* err);
 
 }  // namespace bpx
 

@@ -41,6 +41,11 @@ struct GemmParams {
   int32_t wide_split;
   int32_t part_tiles;  // capacity of part in 256 x 256 tiles (0: no split-K)
   float* part;
+  // Two-dimensional form (launch_coded_gemm_2d): data block s = r * grid + c
+  // is A row block r times B column block c; Y slots are Mb x Nb.
+  int32_t grid;
+  int32_t pad1;
+  int64_t Nb;
   // BF16 / BF16x3: B split into transposed bf16 planes (N x kp, k contiguous)
   const unsigned short* bt_hi;
   const unsigned short* bt_lo;
@@ -80,7 +85,11 @@ struct PeelParams {
   int32_t nsteps;
   int32_t nslots;
   int32_t nsubs;  // length of subs
-  int32_t pad;
+  // Block layout: data block s covers C rows (s / grid) * Mb .., columns
+  // (s % grid) * Nb ..; Y slots are Mb x Nb.  grid = 1, Nb = N for row
+  // blocks (the vector form assumes that layout).
+  int32_t grid;
+  int64_t Nb;
 };
 // Bytes of LDS a peel workgroup holds besides its slots: the step program
 // (steps, then subs), staged once per workgroup.
@@ -107,6 +116,8 @@ int32_t gemm_tile_count();
 TileShape gemm_tile_shape(int32_t t);
 
 hipError_t launch_coded_gemm(const GemmParams& p, int32_t tile, hipStream_t stream);
+// FP32 coded GEMM of the two-dimensional form (64 x 128 tiles).
+hipError_t launch_coded_gemm_2d(const GemmParams& p, hipStream_t stream);
 
 int32_t bf16_tile_count();
 TileShape bf16_tile_shape(int32_t t);

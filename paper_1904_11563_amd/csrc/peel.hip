@@ -49,11 +49,20 @@ template <int THREADS>
 __device__ __forceinline__ void peel_block(const PeelParams& p, int64_t block, float* xs,
                                            const PeelStep* steps, const int32_t* subs) {
   const int tid = threadIdx.x;
-  const int64_t total = p.Mb * p.N;
+  const int64_t total = p.Mb * p.Nb;
   const int64_t e = block * THREADS + tid;
   const bool active = e < total;
-  const int64_t r = active ? e / p.N : 0;
-  const int64_t c = active ? e - r * p.N : 0;
+  const int64_t r = active ? e / p.Nb : 0;
+  const int64_t c = active ? e - r * p.Nb : 0;
+  // data block s sits at C rows (s / grid) * Mb + r, column (s % grid) * Nb + c
+  auto c_index = [&](int32_t s) __attribute__((always_inline)) -> int64_t {
+    const int64_t br = s / p.grid, bc = s - br * p.grid;
+    return (br * p.Mb + r) * p.ldc + bc * p.Nb + c;
+  };
+  auto valid = [&](int32_t s) __attribute__((always_inline)) -> bool {
+    const int64_t br = s / p.grid, bc = s - br * p.grid;
+    return br * p.Mb + r < p.M && bc * p.Nb + c < p.N;
+  };
 
   for (int st0 = 0; st0 < p.nsteps; st0 += kBatch) {
     float y[kBatch];
@@ -63,12 +72,11 @@ __device__ __forceinline__ void peel_block(const PeelParams& p, int64_t block, f
       const int st = st0 + i;
       if (st < p.nsteps && active) {
         const PeelStep S = steps[st];
-        const int64_t base = (int64_t)S.s * p.Mb;
-        if (r < valid_rows(p, base)) {
+        if (valid(S.s)) {
           if (S.src >= 0)
             y[i] = p.Y[(int64_t)S.src * total + e];
           else
-            y[i] = p.C[(base + r) * p.ldc + c];
+            y[i] = p.C[c_index(S.s)];
         }
       }
     }
@@ -77,10 +85,9 @@ __device__ __forceinline__ void peel_block(const PeelParams& p, int64_t block, f
       const int st = st0 + i;
       if (st >= p.nsteps) break;
       const PeelStep S = steps[st];
-      const int64_t base = (int64_t)S.s * p.Mb;
-      const int64_t valid = valid_rows(p, base);
+      const bool ok = active && valid(S.s);
       float x = 0.f;
-      if (r < valid) {
+      if (ok) {
         const int32_t* sub = subs + S.sub_off;
         if (S.f64) {
           double acc = (double)y[i];
@@ -98,7 +105,7 @@ __device__ __forceinline__ void peel_block(const PeelParams& p, int64_t block, f
         }
       }
       if (S.slot >= 0) xs[S.slot * THREADS + tid] = x;
-      if (S.write && active && r < valid) p.C[(base + r) * p.ldc + c] = x;
+      if (S.write && ok) p.C[c_index(S.s)] = x;
     }
   }
 }
@@ -212,7 +219,7 @@ hipError_t launch_peel_grouped(const GroupDesc* d, const int64_t* pstart, const 
 // are smaller, uses the vector form.
 hipError_t launch_peel(const PeelParams& p, hipStream_t stream) {
   if (p.nsteps == 0) return hipSuccess;
-  const int64_t total = p.Mb * p.N;
+  const int64_t total = p.Mb * p.Nb;
   int threads = 256;
   if ((int64_t)p.nslots * 256 * 4 > 64 * 1024) threads = 64;
   const size_t lds =

@@ -84,8 +84,8 @@ std::vector<int32_t> symbols_of_columns(const bpx_code& code, const int32_t* col
 }  // namespace
 
 int make_plan(const bpx_code& code, const int32_t* arrival, int32_t n_arrival, int32_t n_lost,
-              int32_t mode, int64_t M, int64_t K, int64_t N, int32_t prec, bpx_plan* plan,
-              std::string* err) {
+              int32_t mode, int64_t M, int64_t K, int64_t N, int32_t prec, int32_t grid,
+              bpx_plan* plan, std::string* err) {
   const int32_t n = code.n, kb = code.kb();
   if (!arrival || n_arrival != n) {
     *err = "arrival must list every column";
@@ -119,7 +119,19 @@ int make_plan(const bpx_code& code, const int32_t* arrival, int32_t n_arrival, i
   plan->M = M;
   plan->K = K;
   plan->N = N;
-  plan->Mb = (M + kb - 1) / kb;
+  if (grid > 1) {
+    if ((int64_t)grid * grid != kb) {
+      *err = "the two-dimensional form needs k*b = grid^2";
+      return BPX_E_INVALID;
+    }
+    plan->grid = grid;
+    plan->Mb = (M + grid - 1) / grid;
+    plan->Nb = N / grid;
+  } else {
+    plan->grid = 1;
+    plan->Mb = (M + kb - 1) / kb;
+    plan->Nb = N;
+  }
 
   const int32_t n_avail = mode == BPX_MODE_ERASURE ? n - n_lost : n;
   std::vector<int32_t> syms;

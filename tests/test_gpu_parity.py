@@ -259,6 +259,71 @@ def test_construction_b_codes_exact_and_full_size_sampled():
     assert e <= TOL_F32
 
 
+def test_two_dimensional_form_exact_and_products():
+    """The two-dimensional form (A by rows, B by columns, symbols of block
+    products): integer operands decode exactly for every erasure pattern of
+    Tables I and III that peels (ragged M, K not a multiple of 32, Nb not a
+    multiple of the tile), and every coded product, gray symbols included,
+    equals the oracle's (sum of its members' block products)."""
+    from oracle import pipeline2d
+    for lib, oc, M, K, N in ((bpx.Code.table1(), ocodes.table1(), 37, 68, 200),
+                             (bpx.Code.table3(), ocodes.table3(), 50, 100, 264)):
+        A = inputs.integers(50, inputs.TAG_A, (M, K))
+        B = inputs.integers(50, inputs.TAG_B, (K, N))
+        R = A.astype(np.float64) @ B.astype(np.float64)
+        n_ok = 0
+        for lost in itertools.combinations(range(5), 2):
+            order = [j for j in range(5) if j not in lost] + list(lost)
+            plan = bpx.Plan(lib, order, 2, bpx.MODE_ERASURE, M, K, N, two_d=True)
+            if not plan.decodable:
+                continue
+            _say("2-D", lib.info()["k"], lost)
+            assert np.array_equal(run(plan, A, B).astype(np.float64), R), lost
+            n_ok += 1
+        assert n_ok >= 1
+        # every symbol's product, FULL mode
+        plan = bpx.Plan(lib, [0, 1, 2, 3, 4], 0, bpx.MODE_FULL, M, K, N, two_d=True)
+        grid, Nb = plan.grid()
+        Mb = plan.info()["Mb"]
+        sch = plan.schedule()
+        Cd = torch.zeros((M, N), device="cuda")
+        ws = bpx.alloc_workspace(plan)
+        bpx.coded_gemm(plan, dev(A), dev(B), Cd, ws)
+        Y = host(ws).view(np.float32)
+        C = host(Cd)
+        want = pipeline2d.coded_products(A, B, oc, sch["computed"].tolist())
+        sym = {g: d for g, _, d in oc.symbols()}
+        for g, d in zip(sch["computed"].tolist(), sch["dest"].tolist()):
+            if d >= 0:
+                got = Y[d * Mb * Nb:(d + 1) * Mb * Nb].reshape(Mb, Nb).astype(np.float64)
+                assert np.array_equal(got, want[g]), (g, pipeline2d.kind(sym[g], grid))
+            else:
+                r, c = divmod(-1 - d, grid)
+                rows = min(Mb, M - r * Mb)
+                got = C[r * Mb:r * Mb + rows, c * Nb:(c + 1) * Nb].astype(np.float64)
+                assert np.array_equal(got, want[g][:rows]), g
+
+
+def test_two_dimensional_form_float_tolerance():
+    """The (12,8,2) searched code in the two-dimensional form (4 x 4 block
+    grid, gray symbols present) on float operands: relative Frobenius error
+    against float64 within the FP32 bound, straggler arrivals."""
+    from oracle import pipeline2d
+    code = lib_code(inputs.CODE_1282)
+    oc = oracle_of(code)
+    assert pipeline2d.gray_ratio(oc) > 0
+    M, K, N = 1000, 520, 1024
+    A = inputs.normal(51, inputs.TAG_A, (M, K))
+    B = inputs.normal(51, inputs.TAG_B, (K, N))
+    R = pipeline.uncoded(A, B)
+    for seed in range(3):
+        arrival, _ = inputs.shifted_exp_arrival(seed, 12)
+        plan = bpx.Plan(code, arrival, 0, bpx.MODE_STRAGGLER, M, K, N, two_d=True)
+        e = relf(run(plan, A, B), R)
+        _say("2-D float", seed, plan.info(), e)
+        assert e <= TOL_F32
+
+
 def test_identity_code_is_plain_gemm():
     code = bpx.Code.identity(4, 2)
     M, K, N = 203, 100, 77

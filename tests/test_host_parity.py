@@ -210,3 +210,42 @@ def test_workspace_bytes():
     pn = bpx.Plan(c, [3, 4, 0, 1, 2], 0, bpx.MODE_FULL, 9 * 250, 64, 512)
     dn = pn.schedule()["dest"]
     assert pn.workspace_bytes()[0] == al(int((dn >= 0).sum()) * 250 * 512 * 4)
+
+
+def test_two_dimensional_plans():
+    """bpx_plan_create2d: the schedule is the row-block one (peeling depends
+    only on the code), the block grid follows the two-dimensional form
+    (Mb = ceil(M/grid), Nb = N/grid), Y slots are Mb x Nb, and shapes the
+    form does not take are refused."""
+    for lib_code, ocode in ((bpx.Code.table1(), codes.table1()),
+                            (bpx.Code.table3(), codes.table3())):
+        m = int(round(ocode.kb ** 0.5))
+        M, K, N = 23, 12, 8 * m
+        for order in list(permutations(range(5)))[::7]:
+            for lost in range(0, 3):
+                p1 = bpx.Plan(lib_code, list(order), lost, bpx.MODE_ERASURE, M, K, N)
+                p2 = bpx.Plan(lib_code, list(order), lost, bpx.MODE_ERASURE, M, K, N,
+                              two_d=True)
+                s1, s2 = p1.schedule(), p2.schedule()
+                for key in ("computed", "dest", "releaser", "depth", "sub_ptr", "sub_data"):
+                    assert np.array_equal(s1[key], s2[key]), key
+                assert p2.grid() == (m, N // m)
+                assert p1.grid() == (1, N)
+                assert p2.info()["Mb"] == -(-M // m)
+                want = make_plan(ocode, list(order), lost, bpx.MODE_ERASURE)
+                assert p2.decodable == want.decodable
+                if p2.decodable:
+                    al = lambda x: -(-x // 256) * 256
+                    n_y = int((s2["dest"] >= 0).sum())
+                    assert p2.workspace_bytes()[0] == al(n_y * (-(-M // m)) * (N // m) * 4)
+    t1 = bpx.Code.table1()
+    for (K, N, prec, status) in ((12, 6, bpx.PREC_F32, bpx.E_UNSUPPORTED),   # N/grid = 3
+                                 (10, 16, bpx.PREC_F32, bpx.E_UNSUPPORTED),  # K % 4
+                                 (12, 16, bpx.PREC_BF16X3, bpx.E_UNSUPPORTED)):
+        with pytest.raises(bpx.BpxError) as e:
+            bpx.Plan(t1, [0, 1, 2, 3, 4], 0, bpx.MODE_STRAGGLER, 8, K, N, prec, two_d=True)
+        assert e.value.status == status
+    with pytest.raises(bpx.BpxError) as e:    # k*b = 8 is not a square
+        bpx.Plan(bpx.Code.identity(4, 2), [0, 1, 2, 3], 0, bpx.MODE_STRAGGLER, 8, 8, 16,
+                 two_d=True)
+    assert e.value.status == bpx.E_INVALID
