@@ -13,7 +13,8 @@ timed region, and the float64 oracle on the host for a bounded sample.
 
 Other workloads (--workload): fp32_small, bf16_small (split-BF16x3),
 fp8_mojette (FP8x2, Mojette Construction A), mojette_b (FP32, Mojette
-Construction B at the headline's shape), batch (256 uneven products, one
+Construction B at the headline's shape), fp32_2d (FP32, the two-dimensional
+form: A row blocks times B column blocks), batch (256 uneven products, one
 grouped launch sequence captured in a HIP graph).
 
 Prints ONE JSON line.
@@ -42,7 +43,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="fp32_scale",
                     choices=["fp32_scale", "fp32_small", "bf16_small", "fp8_mojette", "mojette_b",
-                             "batch"])
+                             "fp32_2d", "batch"])
     ap.add_argument("--prec", default=None, help="override the workload's precision")
     ap.add_argument("--mode", default="arrival", choices=["arrival", "full", "min"])
     ap.add_argument("--seed", type=int, default=0)
@@ -149,7 +150,8 @@ def run_single(args):
     else:
         mode = bpx.MODE_STRAGGLER if mode_name == "straggler" else bpx.MODE_ERASURE
     t0 = time.perf_counter()
-    plan = bpx.Plan(code, arrival, lost, mode, w.M, w.K, w.N, prec)
+    two_d = bool(w.extra.get("two_d"))
+    plan = bpx.Plan(code, arrival, lost, mode, w.M, w.K, w.N, prec, two_d=two_d)
     plan_us = (time.perf_counter() - t0) * 1e6
     info = plan.info()
     if not info["decodable"]:
@@ -203,7 +205,7 @@ def run_single(args):
         ref_prec = bpx.PREC_BF16 if prec_name.startswith("fp8") else prec
         ident = bpx.Code.identity(spec.k, spec.b)
         uplan = bpx.Plan(ident, list(range(spec.k)), 0, bpx.MODE_STRAGGLER, w.M, w.K, w.N,
-                         ref_prec)
+                         prec=ref_prec, two_d=two_d)
         uplan.upload()
         uws = bpx.alloc_workspace(uplan, dev)
         Cu = torch.empty_like(Cd)
@@ -237,12 +239,23 @@ def run_single(args):
                                                    refs["uncoded_torch_tflops"])
         refs["frac_of_uncoded_own"] = value / refs["uncoded_own_tflops"]
 
-    hbm = hbm_kernels(torch, bpx, plan, code, Ad, Cd, ws, w, info, args.steps)
+    hbm = hbm_kernels(torch, bpx, plan, code, Ad, Cd, ws, w, info, args.steps, two_d)
 
     n_comp = info["n_computed"]
     gemm_flops = 2.0 * Mb * w.K * w.N * n_comp
+    if two_d:   # Mb x Nb products; a gray symbol takes one pass per member
+        grid, Nb = plan.grid()
+        col_ptr, sym_ptr, sym_data = code.csr()
+        passes = 0
+        for g in plan.schedule()["computed"].tolist():
+            mem = [int(x) for x in sym_data[sym_ptr[g]:sym_ptr[g + 1]]]
+            rs, cs = {x // grid for x in mem}, {x % grid for x in mem}
+            passes += 1 if (len(rs) == 1 or len(cs) == 1) else len(mem)
+        gemm_flops = 2.0 * Mb * w.K * Nb * passes
     achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12
-    if Mb % 256 == 0 and w.N % 256 == 0 and w.K % 32 == 0 and w.M % Mb == 0:
+    if two_d:
+        f32_kernel = "coded_gemm_2d_kernel (64x128 tiles of block products)"
+    elif Mb % 256 == 0 and w.N % 256 == 0 and w.K % 32 == 0 and w.M % Mb == 0:
         f32_kernel = ("coded_gemm_f32_wide_kernel<4,2> (full rounds of 256x256 tiles; a short "
                       "last round split along K + splitk_reduce_kernel, or as "
                       "coded_gemm_f32_kernel<64,128,32,2> sub-tiles), one call")
@@ -268,8 +281,12 @@ def run_single(args):
                 "roofline": roofline, "hbm": hbm})
     out.update(refs)
     out["latency_model"] = latency_model(bpx, code, w, prec, gemm_ms, n_comp, hbm, refs, spec)
+    if two_d:
+        cfg["form"] = "two-dimensional (A row blocks x B column blocks)"
+        cfg["grid"] = plan.grid()[0]
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_single(A, B, code, arrival, lost, mode, w, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_single(A, B, code, arrival, lost, mode, w, args.cpu_seconds,
+                                         two_d)
     return out
 
 
@@ -282,8 +299,10 @@ def latency_model(bpx, code, w, prec, gemm_ms, n_comp, hbm, refs, spec, samples=
     gbps = hbm["peel"]["GBps"]
     res = {"unit": "us", "mu": 1.0, "model": "column done when its b products are; "
            "prefix from the library planner; encode fused into the products"}
+    two_d = bool(w.extra.get("two_d"))
     lm = latency.summary(latency.sample(bpx, code, w.M, w.K, w.N, gemm_ms * 1e-3 / n_comp,
-                                        gbps * 1e9 if gbps else None, samples=samples, prec=prec))
+                                        gbps * 1e9 if gbps else None, samples=samples, prec=prec,
+                                        two_d=two_d))
     res["coded"] = {k: (v * 1e6 if k in ("E_T", "encode", "cluster", "decode") else v)
                     for k, v in lm.items()}
     if refs.get("uncoded_own_tflops"):
@@ -291,54 +310,59 @@ def latency_model(bpx, code, w, prec, gemm_ms, n_comp, hbm, refs, spec, samples=
         t_u = 2.0 * w.M * w.K * w.N / (refs["uncoded_own_tflops"] * 1e12) / kb
         ident = bpx.Code.identity(spec.k, spec.b)
         lu = latency.summary(latency.sample(bpx, ident, w.M, w.K, w.N, t_u, None,
-                                            samples=samples, prec=prec))
+                                            samples=samples, prec=prec, two_d=two_d))
         res["uncoded"] = {k: (v * 1e6 if k in ("E_T", "encode", "cluster", "decode") else v)
                           for k, v in lu.items()}
     return res
 
 
-def hbm_kernels(torch, bpx, plan, code, Ad, Cd, ws, w, info, steps):
+def hbm_kernels(torch, bpx, plan, code, Ad, Cd, ws, w, info, steps, two_d=False):
     """Achieved HBM GB/s of the two streaming kernels: the standalone encode
     (bpx_encode) and the peel, each as algorithmic bytes / event time."""
     sch = plan.schedule()
     col_ptr, sym_ptr, sym_data = code.csr()
     Mb, K, N, M = info["Mb"], w.K, w.N, w.M
-    rows = lambda s: max(0, min(Mb, M - s * Mb))
-    comp = sch["computed"].tolist()
-    enc_read = sum(rows(int(s)) * K * 4 for g in comp for s in sym_data[sym_ptr[g]:sym_ptr[g + 1]])
-    enc_write = len(comp) * Mb * K * 4
-    _, enc_bytes = plan.workspace_bytes()
-    out_enc = torch.empty(enc_bytes // 4, dtype=torch.float32, device=Ad.device)
-    bpx.encode(plan, Ad, out_enc)
-    enc_ms = timed(torch, lambda: bpx.encode(plan, Ad, out_enc), steps)
-    del out_enc
     from paper_1904_11563_amd.latency import peel_bytes
     rd, wr = peel_bytes(plan, M, N)
     peel_ms = timed(torch, lambda: bpx.peel_decode(plan, ws, Cd), steps)
     res = {"peak_GBps": 8000.0}
-    for name, b, t in (("encode", enc_read + enc_write, enc_ms), ("peel", rd + wr, peel_ms)):
+    legs = [("peel", rd + wr, peel_ms)]
+    if not two_d:   # the stand-alone encode exists for row-block plans
+        rows = lambda s: max(0, min(Mb, M - s * Mb))
+        comp = sch["computed"].tolist()
+        enc_read = sum(rows(int(s)) * K * 4 for g in comp
+                       for s in sym_data[sym_ptr[g]:sym_ptr[g + 1]])
+        enc_write = len(comp) * Mb * K * 4
+        _, enc_bytes = plan.workspace_bytes()
+        out_enc = torch.empty(enc_bytes // 4, dtype=torch.float32, device=Ad.device)
+        bpx.encode(plan, Ad, out_enc)
+        enc_ms = timed(torch, lambda: bpx.encode(plan, Ad, out_enc), steps)
+        del out_enc
+        legs.insert(0, ("encode", enc_read + enc_write, enc_ms))
+    for name, b, t in legs:
         res[name] = {"bytes": b, "ms": t, "GBps": b / (t * 1e-3) / 1e9 if t > 0 else None,
                      "frac": (b / (t * 1e-3) / 1e9) / 8000.0 if t > 0 else None}
     return res
 
 
-def cpu_single(A, B, code, arrival, lost, mode, w, budget):
+def cpu_single(A, B, code, arrival, lost, mode, w, budget, two_d=False):
     """The float64 oracle's coded pipeline on A and the first columns of B,
     the column count scaled so the run takes about `budget` seconds."""
     import numpy as np
 
-    from oracle import pipeline
+    from oracle import pipeline, pipeline2d
     from oracle.peeling import make_plan
     oc = oracle_code(code)
     ref_plan = make_plan(oc, list(arrival), lost, mode)
+    ref = pipeline2d.coded_matmul_ref if two_d else pipeline.coded_matmul_ref
     cols = min(64, w.N)
     t0 = time.perf_counter()
-    pipeline.coded_matmul_ref(A, np.ascontiguousarray(B[:, :cols]), oc, ref_plan)
+    ref(A, np.ascontiguousarray(B[:, :cols]), oc, ref_plan)
     dt = time.perf_counter() - t0
     more = int(cols * budget / max(dt, 1e-3))
     cols = max(cols, min(w.N, more - more % 64))
     t0 = time.perf_counter()
-    pipeline.coded_matmul_ref(A, np.ascontiguousarray(B[:, :cols]), oc, ref_plan)
+    ref(A, np.ascontiguousarray(B[:, :cols]), oc, ref_plan)
     dt = time.perf_counter() - t0
     useful = 2.0 * w.M * w.K * cols
     return {"value": useful / dt / 1e12, "unit": "TFLOP/s", "cores": blas_threads(),

@@ -100,6 +100,10 @@ WORKLOADS = {
     # columns erased
     "mojette_b": Workload("mojette_b", 8192, 8192, 4096, CODE_MOJ_B, "f32", "normal",
                           "erasure:4"),
+    # the two-dimensional form: A in 4 row blocks, B in 4 column blocks, the
+    # (12,8,2) code over the 4 x 4 grid of block products
+    "fp32_2d": Workload("fp32_2d", 8192, 8192, 8192, CODE_1282, "f32", "normal", "shiftexp",
+                        extra={"two_d": True}),
 }
 
 

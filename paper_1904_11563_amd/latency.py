@@ -35,16 +35,17 @@ def peel_bytes(plan, M: int, N: int):
     subtracts it."""
     sch = plan.schedule()
     Mb = plan.info()["Mb"]
-    rows = lambda s: max(0, min(Mb, M - s * Mb))
+    grid, Nb = plan.grid()           # block s: rows of block row s // grid
+    rows = lambda s: max(0, min(Mb, M - (s // grid) * Mb))
     dest = dict(zip(sch["computed"].tolist(), sch["dest"].tolist()))
     used = set(sch["sub_data"].tolist())
     rd = wr = 0
     for s, g in enumerate(sch["releaser"].tolist()):
         d = dest[g]
         if d >= 0 or s in used:
-            rd += rows(s) * N * 4
+            rd += rows(s) * Nb * 4
         if d >= 0:
-            wr += rows(s) * N * 4
+            wr += rows(s) * Nb * 4
     return rd, wr
 
 
@@ -61,7 +62,7 @@ class LatencySample:
 
 
 def sample(bpx, code, M, K, N, t_unit, peel_bytes_per_s, t_encode=0.0, mu=1.0, samples=1000,
-           seed=0, prec=None):
+           seed=0, prec=None, two_d=False):
     """Monte Carlo of T over `samples` draws of the processors' task times.
     t_unit: seconds per coded product; peel_bytes_per_s: measured peel
     bandwidth (None or 0: T_d = 0).  Returns the list of LatencySample."""
@@ -75,7 +76,7 @@ def sample(bpx, code, M, K, N, t_unit, peel_bytes_per_s, t_encode=0.0, mu=1.0, s
         x = rng.exponential(1.0 / mu, size=(n, b))
         t_col = t_unit * x.max(axis=1)
         order = np.argsort(t_col, kind="stable").astype(np.int32)
-        plan = bpx.Plan(code, order, 0, bpx.MODE_STRAGGLER, M, K, N, prec)
+        plan = bpx.Plan(code, order, 0, bpx.MODE_STRAGGLER, M, K, N, prec, two_d=two_d)
         m = plan.info()["prefix_m"]
         if not plan.decodable:
             raise ValueError("the code does not decode from all of its columns")
