@@ -58,12 +58,15 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_source_hash():
+GEMM_SOURCE = {"f32": "gemm_f32.hip", "bf16": "gemm_bf16.hip", "bf16x3": "gemm_bf16.hip",
+               "fp8": "gemm_fp8.hip", "fp8x2": "gemm_fp8.hip"}
+
+
+def kernel_source_hash(prec):
+    """Hash of the source file that holds the precision's GEMM kernels."""
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1904_11563_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.startswith("gemm") and f.endswith(".hip"):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    h.update(open(os.path.join(ROOT, "paper_1904_11563_amd", "csrc", GEMM_SOURCE[prec]),
+                  "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -75,7 +78,7 @@ def load_traffic(workload, prec):
         return None
     try:
         e = json.load(open(path))[f"{workload}:{prec}"]
-        if e.get("gemm_source") != kernel_source_hash():
+        if e.get("gemm_source") != kernel_source_hash(prec):
             return None
         return e["bytes_per_launch"]
     except Exception:

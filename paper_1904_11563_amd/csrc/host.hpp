@@ -30,7 +30,8 @@ struct PeelStep {
   int32_t f64;      // 1: accumulate in FP64 (depth > 4), 0: FP32 Kahan
   int32_t slot;     // LDS slot that keeps X_s for later steps, or -1
   int32_t write;    // 1: write X_s to C
-  int32_t pad;
+  int32_t brow;     // block row of s (s itself for row blocks)
+  int32_t bcol;     // block column of s (0 for row blocks)
 };
 
 struct bpx_plan {

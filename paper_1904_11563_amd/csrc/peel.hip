@@ -54,14 +54,12 @@ __device__ __forceinline__ void peel_block(const PeelParams& p, int64_t block, f
   const bool active = e < total;
   const int64_t r = active ? e / p.Nb : 0;
   const int64_t c = active ? e - r * p.Nb : 0;
-  // data block s sits at C rows (s / grid) * Mb + r, column (s % grid) * Nb + c
-  auto c_index = [&](int32_t s) __attribute__((always_inline)) -> int64_t {
-    const int64_t br = s / p.grid, bc = s - br * p.grid;
-    return (br * p.Mb + r) * p.ldc + bc * p.Nb + c;
+  // data block s sits at C rows brow * Mb + r, column bcol * Nb + c
+  auto c_index = [&](const PeelStep& S) __attribute__((always_inline)) -> int64_t {
+    return ((int64_t)S.brow * p.Mb + r) * p.ldc + (int64_t)S.bcol * p.Nb + c;
   };
-  auto valid = [&](int32_t s) __attribute__((always_inline)) -> bool {
-    const int64_t br = s / p.grid, bc = s - br * p.grid;
-    return br * p.Mb + r < p.M && bc * p.Nb + c < p.N;
+  auto valid = [&](const PeelStep& S) __attribute__((always_inline)) -> bool {
+    return (int64_t)S.brow * p.Mb + r < p.M && (int64_t)S.bcol * p.Nb + c < p.N;
   };
 
   for (int st0 = 0; st0 < p.nsteps; st0 += kBatch) {
@@ -72,11 +70,11 @@ __device__ __forceinline__ void peel_block(const PeelParams& p, int64_t block, f
       const int st = st0 + i;
       if (st < p.nsteps && active) {
         const PeelStep S = steps[st];
-        if (valid(S.s)) {
+        if (valid(S)) {
           if (S.src >= 0)
             y[i] = p.Y[(int64_t)S.src * total + e];
           else
-            y[i] = p.C[c_index(S.s)];
+            y[i] = p.C[c_index(S)];
         }
       }
     }
@@ -85,7 +83,7 @@ __device__ __forceinline__ void peel_block(const PeelParams& p, int64_t block, f
       const int st = st0 + i;
       if (st >= p.nsteps) break;
       const PeelStep S = steps[st];
-      const bool ok = active && valid(S.s);
+      const bool ok = active && valid(S);
       float x = 0.f;
       if (ok) {
         const int32_t* sub = subs + S.sub_off;
@@ -105,7 +103,7 @@ __device__ __forceinline__ void peel_block(const PeelParams& p, int64_t block, f
         }
       }
       if (S.slot >= 0) xs[S.slot * THREADS + tid] = x;
-      if (S.write && ok) p.C[c_index(S.s)] = x;
+      if (S.write && ok) p.C[c_index(S)] = x;
     }
   }
 }

@@ -245,6 +245,8 @@ int make_plan(const bpx_code& code, const int32_t* arrival, int32_t n_arrival, i
       st.f64 = plan->depth[s] > 4 ? 1 : 0;
       st.slot = slot[s];
       st.write = dst >= 0 ? 1 : 0;
+      st.brow = s / plan->grid;
+      st.bcol = s % plan->grid;
       if (st.src < 0 && st.slot < 0) continue;  // copy in place, never reused
       for (int32_t e = plan->sub_ptr[s]; e < plan->sub_ptr[s + 1]; ++e)
         plan->step_subs.push_back(slot[plan->sub_data[e]]);
