@@ -212,11 +212,30 @@ hipError_t launch_peel_grouped(const GroupDesc* d, const int64_t* pstart, const 
   return hipGetLastError();
 }
 
-// Single products take the scalar form: measured faster than the vector
-// form on the 8192 x 4096 FP32 workload; the grouped peel, whose products
-// are smaller, uses the vector form.
+// Single products take the vector form (128 threads: 74 us on the
+// 8192 x 4096 FP32 workload, against 87 us for the scalar form with 256
+// threads) when N and ldc are multiples of 4 and the blocks are row blocks;
+// otherwise the scalar form, which also handles the block grid of the
+// two-dimensional form.
+// Single product, row blocks, N and ldc multiples of 4: the vector form.
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void peel4s_kernel(PeelParams p) {
+  extern __shared__ v4f xs4s[];
+  int32_t* prog = reinterpret_cast<int32_t*>(xs4s + (size_t)p.nslots * THREADS);
+  stage_program(p, prog, THREADS);
+  peel_block4<THREADS>(p, blockIdx.x, xs4s, reinterpret_cast<const PeelStep*>(prog),
+                       prog + p.nsteps * (int)(sizeof(PeelStep) / 4));
+}
 hipError_t launch_peel(const PeelParams& p, hipStream_t stream) {
   if (p.nsteps == 0) return hipSuccess;
+  if (p.grid == 1 && (p.N & 3) == 0 && (p.ldc & 3) == 0) {
+    const size_t lds = (size_t)p.nslots * 128 * 16 + peel_program_bytes(p.nsteps, p.nsubs);
+    const int64_t blocks = (p.Mb * (p.N / 4) + 127) / 128;
+    if (lds <= 160 * 1024 && blocks <= 0x7fffffff) {
+      hipLaunchKernelGGL(peel4s_kernel<128>, dim3((unsigned)blocks), dim3(128), lds, stream, p);
+      return hipGetLastError();
+    }
+  }
   const int64_t total = p.Mb * p.Nb;
   int threads = 256;
   if ((int64_t)p.nslots * 256 * 4 > 64 * 1024) threads = 64;
