@@ -51,26 +51,72 @@ __device__ __forceinline__ v4f from_bf16(v4bf x) {
 // ------------------------------------------------------------- B split ---
 // Bt_hi[n][k] = bf16(B[k][n]); Bt_lo[n][k] = bf16(B[k][n] - Bt_hi[n][k]);
 // k in [K, Kp) is zero.  64 x 64 tiles transposed through LDS.
-__global__ __launch_bounds__(256) void split_b_kernel(const float* B, int64_t ldb, int64_t K,
-                                                      int64_t N, int64_t Kp, us* bt_hi, us* bt_lo) {
-  __shared__ float t[64][65];
-  const int64_t k0 = (int64_t)blockIdx.y * 64, n0 = (int64_t)blockIdx.x * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  for (int r = ty; r < 64; r += 4) {
-    const int64_t k = k0 + r, n = n0 + tx;
-    t[r][tx] = (k < K && n < N) ? B[k * ldb + n] : 0.f;
+//
+// LDS rows of 64 floats, unpadded, with the columns of k-row r stored at
+// n ^ tsw(r).  The staging writes are 128-bit (8 consecutive lanes per
+// 32-bank pass on gfx950: 8 distinct 16-byte slots of one row) and the
+// transposed reads 32-bit (32 lanes per 32-bank pass: lanes of one pass read
+// column nl of rows 16 a + j for a = 0..3, which the swizzle spreads over
+// four distinct 8-bank groups).  Rows padded to 65 floats left both sides
+// with 2-way conflicts.
+__device__ __forceinline__ int tsw(int r) { return ((r >> 4) & 3) << 3; }
+
+// Needs B 16-byte aligned, ldb a multiple of 4 and Kp a multiple of 16 (the
+// library's argument checks and plan shapes guarantee all three).
+__device__ __forceinline__ void split_b_tile(const float* B, int64_t ldb, int64_t K, int64_t N,
+                                             int64_t Kp, us* bt_hi, us* bt_lo, int64_t k0,
+                                             int64_t n0, float* t) {
+  const int tid = threadIdx.x;
+  // read: thread owns float4 (row kr, columns nc .. nc+3), four rows apart
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int f = tid + 256 * i;
+    const int kr = f >> 4, nc = (f & 15) * 4;
+    const int64_t k = k0 + kr, n = n0 + nc;
+    v4f v = {0.f, 0.f, 0.f, 0.f};
+    if (k < K) {
+      const float* src = B + k * ldb + n;
+      if (n + 3 < N) {
+        v = *reinterpret_cast<const v4f*>(src);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (n + e < N) v[e] = src[e];
+      }
+    }
+    *reinterpret_cast<v4f*>(t + kr * 64 + (nc ^ tsw(kr))) = v;
   }
   __syncthreads();
-  for (int r = ty; r < 64; r += 4) {
-    const int64_t n = n0 + r, k = k0 + tx;
-    if (n < N && k < Kp) {
-      const float x = t[tx][r];
-      const __bf16 h = (__bf16)x;
-      const __bf16 l = (__bf16)(x - (float)h);
-      bt_hi[n * Kp + k] = __builtin_bit_cast(us, h);
-      if (bt_lo) bt_lo[n * Kp + k] = __builtin_bit_cast(us, l);
-    }
+  // write: thread owns output row n = tid / 4, k kq .. kq+15 (two 16-byte
+  // pieces per plane)
+  const int nl = tid >> 2, kq = (tid & 3) * 16;
+  const int64_t n = n0 + nl, k = k0 + kq;
+  if (n >= N || k >= Kp) return;
+  unsigned hw[8], lw[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int r = kq + 2 * j;  // rows r, r + 1 share the swizzle
+    const float x0 = t[r * 64 + (nl ^ tsw(r))], x1 = t[(r + 1) * 64 + (nl ^ tsw(r))];
+    const __bf16 h0 = (__bf16)x0, h1 = (__bf16)x1;
+    const __bf16 l0 = (__bf16)(x0 - (float)h0), l1 = (__bf16)(x1 - (float)h1);
+    hw[j] = (unsigned)__builtin_bit_cast(us, h0) | ((unsigned)__builtin_bit_cast(us, h1) << 16);
+    lw[j] = (unsigned)__builtin_bit_cast(us, l0) | ((unsigned)__builtin_bit_cast(us, l1) << 16);
   }
+  uint4* hp = reinterpret_cast<uint4*>(bt_hi + n * Kp + k);
+  hp[0] = uint4{hw[0], hw[1], hw[2], hw[3]};
+  hp[1] = uint4{hw[4], hw[5], hw[6], hw[7]};
+  if (bt_lo) {
+    uint4* lp = reinterpret_cast<uint4*>(bt_lo + n * Kp + k);
+    lp[0] = uint4{lw[0], lw[1], lw[2], lw[3]};
+    lp[1] = uint4{lw[4], lw[5], lw[6], lw[7]};
+  }
+}
+
+__global__ __launch_bounds__(256) void split_b_kernel(const float* B, int64_t ldb, int64_t K,
+                                                      int64_t N, int64_t Kp, us* bt_hi, us* bt_lo) {
+  __shared__ __attribute__((aligned(16))) float t[64 * 64];
+  split_b_tile(B, ldb, K, N, Kp, bt_hi, bt_lo, (int64_t)blockIdx.y * 64,
+               (int64_t)blockIdx.x * 64, t);
 }
 
 // -------------------------------------------------------------- GEMM ---
@@ -311,10 +357,15 @@ namespace flat {
 constexpr int BM = 128, BN = 256, NT = 512;
 constexpr int TM = 64, TN = 64, FM = 4, FN = 4;  // wave tile (2 x 4 waves)
 constexpr int FKS = BK;  // LDS row: 32 bf16 = four 16-byte granules, no padding
-// Granule g of row r sits in slot g ^ ((r >> 2) & 3): the 16 rows read by a
-// k group and the 4 rows written per 256 bytes then cover all 64 banks.
+// Granule g of row r sits in slot g ^ ((r >> 1) & 2).  gfx950 serves a
+// 128-bit LDS read to 16 lanes at a time over 64 banks, the 16 being the
+// lanes that agree in lane bit 5 and in the parity of lane bits 2..4, and a
+// 128-bit write to 8 consecutive lanes over 32 banks.  A fragment read
+// (lane 16 q + c: row c, granule q) then puts each such group of 16 on
+// distinct bank quads, and a B store (4 lanes per row) each group of 8; the
+// swizzle g ^ ((r >> 2) & 3) left two lanes on a quad in every read.
 __device__ __forceinline__ int swz(int row, int granule) {
-  return row * FKS + ((granule ^ ((row >> 2) & 3)) << 3);
+  return row * FKS + ((granule ^ ((row >> 1) & 2)) << 3);
 }
 constexpr int A_PLANE = BM * FKS, B_PLANE = BN * FKS;
 constexpr int UA = BM * BK / 4 / NT;        // float4 of A per thread per member (2)
@@ -553,57 +604,13 @@ __global__ __launch_bounds__(kThreads, OCC) void coded_gemm_bf16_kernel(GemmPara
 __global__ __launch_bounds__(256) void split_b_grouped_kernel(const GroupDesc* d,
                                                               const int64_t* bstart,
                                                               const int32_t* bmap) {
+  __shared__ __attribute__((aligned(16))) float t[64 * 64];
   const int64_t b = blockIdx.x;
   const int lo = bmap[b];
   const GroupDesc& g = d[lo];
   const int64_t r = b - bstart[lo];
-  const int64_t k0 = (r / g.b_tn) * 64, n0 = (r % g.b_tn) * 64;
-  __shared__ float t[64][65];
-  const int tid = threadIdx.x;
-  const int64_t K = g.g.K, N = g.g.N, Kp = g.g.kp, ldb = g.g.ldb;
-  // read: thread owns float4 (row kr, columns nc .. nc+3), four rows apart
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int f = tid + 256 * i;
-    const int kr = f >> 4, nc = (f & 15) * 4;
-    const int64_t k = k0 + kr, n = n0 + nc;
-    v4f v = {0.f, 0.f, 0.f, 0.f};
-    if (k < K) {
-      const float* src = g.g.B + k * ldb + n;
-      if (n + 3 < N) {
-        v = *reinterpret_cast<const v4f*>(src);
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (n + e < N) v[e] = src[e];
-      }
-    }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) t[kr][nc + e] = v[e];
-  }
-  __syncthreads();
-  // write: thread owns output row n = tid / 4, k kq .. kq+15 (two 16-byte
-  // pieces per plane)
-  const int nl = tid >> 2, kq = (tid & 3) * 16;
-  const int64_t n = n0 + nl, k = k0 + kq;
-  if (n >= N || k >= Kp) return;
-  unsigned hw[8], lw[8];
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const float x0 = t[kq + 2 * j][nl], x1 = t[kq + 2 * j + 1][nl];
-    const __bf16 h0 = (__bf16)x0, h1 = (__bf16)x1;
-    const __bf16 l0 = (__bf16)(x0 - (float)h0), l1 = (__bf16)(x1 - (float)h1);
-    hw[j] = (unsigned)__builtin_bit_cast(us, h0) | ((unsigned)__builtin_bit_cast(us, h1) << 16);
-    lw[j] = (unsigned)__builtin_bit_cast(us, l0) | ((unsigned)__builtin_bit_cast(us, l1) << 16);
-  }
-  uint4* hp = reinterpret_cast<uint4*>(const_cast<us*>(g.g.bt_hi) + n * Kp + k);
-  hp[0] = uint4{hw[0], hw[1], hw[2], hw[3]};
-  hp[1] = uint4{hw[4], hw[5], hw[6], hw[7]};
-  if (g.g.bt_lo) {
-    uint4* lp = reinterpret_cast<uint4*>(const_cast<us*>(g.g.bt_lo) + n * Kp + k);
-    lp[0] = uint4{lw[0], lw[1], lw[2], lw[3]};
-    lp[1] = uint4{lw[4], lw[5], lw[6], lw[7]};
-  }
+  split_b_tile(g.g.B, g.g.ldb, g.g.K, g.g.N, g.g.kp, const_cast<us*>(g.g.bt_hi),
+               const_cast<us*>(g.g.bt_lo), (r / g.b_tn) * 64, (r % g.b_tn) * 64, t);
 }
 
 // Persistent grouped GEMM: workgroup w takes tiles w, w + grid, w + 2 grid, ...

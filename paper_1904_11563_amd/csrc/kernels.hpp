@@ -72,6 +72,7 @@ struct Fp8Params {
   float* sa;
   unsigned char* bq;
   float* sb;
+  int32_t group_m;  // wide tiles: row panels per group of the tile order (0: default)
 };
 
 // Peel: see PeelStep in host.hpp.
