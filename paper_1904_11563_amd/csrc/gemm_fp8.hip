@@ -346,9 +346,8 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const unsigned char* base
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<unsigned char*>(base), (short)0, -1,
                                            kRsrcWord3);
 }
-__device__ __forceinline__ v4u bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  return __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
-}
+typedef __attribute__((address_space(3))) void* lds_addr;
+__device__ __forceinline__ lds_addr lds_ptr(unsigned char* p) { return (lds_addr)p; }
 }  // namespace wide8
 
 // Tile order of the wide kernel: each XCD takes a contiguous range of tile
@@ -378,7 +377,11 @@ __global__ __launch_bounds__(wide8::NT, 1) void coded_gemm_fp8_wide_kernel(Fp8Pa
   constexpr int PB = BN * 8 / NT;             // and for B
   constexpr int STAGE = (NA * BM + BN) * CK;  // bytes per LDS stage
   static_assert(TM <= 128 && TN <= 128 && FN % 4 == 0 && PA >= 1, "wave tile");
-  __shared__ __attribute__((aligned(16))) unsigned char lds[2 * STAGE];
+  static_assert(NT / 8 == 64 && BM % 64 == 0 && BN % 64 == 0, "64-row staging groups");
+  // two stages as two arrays: the compiler then sees that a stage being
+  // filled is not the one being read
+  __shared__ __attribute__((aligned(16))) unsigned char lds0[STAGE];
+  __shared__ __attribute__((aligned(16))) unsigned char lds1[STAGE];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
   const int q = lane >> 4, c16 = lane & 15;
@@ -387,40 +390,38 @@ __global__ __launch_bounds__(wide8::NT, 1) void coded_gemm_fp8_wide_kernel(Fp8Pa
   grouped_tile(xcd_remap(blockIdx.x, gridDim.x), p.tiles_m, p.tiles_n, p.group_m, &mt, &nt);
   const int64_t m0 = (int64_t)mt * BM, n0 = (int64_t)nt * BN;
   const int64_t Kp = p.Kp;
-  const int64_t plane = (int64_t)p.n_sym * p.Mbp * Kp;  // bytes per A plane
 
-  // piece f = tid + NT u: row f / 8, bytes (f % 8) * 16 of the 128-byte chunk row
-  const uint32_t voff = (uint32_t)((tid >> 3) * Kp + (tid & 7) * 16);
-  const uint32_t ustep = (uint32_t)((NT / 8) * Kp);
-  v4u ra[NA][PA], rb[PB];
-  auto load = [&](int c) __attribute__((always_inline)) {
+  // Staging by direct loads to LDS: one instruction of a wave fills 64
+  // consecutive 16-byte LDS slots, lane l the slot base + 16 l, and the
+  // global address is the lane's own.  Instruction u of wave w fills rows
+  // 64 u + t of its operand's region, t = 8 w + l / 8, slot l % 8, which
+  // holds granule (l % 8) ^ ((t >> 1) & 5) of that row (the swizzle is its
+  // own inverse and depends on t only).  In the B region, LDS row 64 u + t
+  // holds B row 64 u + nlow(t) (the inverse of b_slot).
+  const int t = 8 * wave + (lane >> 3);
+  const int g = (lane & 7) ^ ((t >> 1) & 5);
+  const uint32_t va = (uint32_t)(t * Kp + g * 16);
+  const uint32_t vb = (uint32_t)((((t & 15) << 2) | (t >> 4)) * Kp + g * 16);
+  const uint32_t step64 = (uint32_t)(64 * Kp);
+  auto dma = [&](unsigned char* st, int c) __attribute__((always_inline)) {
     const int64_t kc = (int64_t)c * CK;
     const auto r0 = rsrc(p.aq + m0 * Kp + kc);
 #pragma unroll
-    for (int u = 0; u < PA; ++u) ra[0][u] = bload(r0, voff, u * ustep);
+    for (int u = 0; u < PA; ++u)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(r0, lds_ptr(st + (64 * u + 8 * wave) * CK), 16, va,
+                                               u * step64, 0, 0);
     if (X2) {
       const auto r1 = rsrc(p.aq2 + m0 * Kp + kc);
 #pragma unroll
-      for (int u = 0; u < PA; ++u) ra[NA - 1][u] = bload(r1, voff, u * ustep);
+      for (int u = 0; u < PA; ++u)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            r1, lds_ptr(st + (BM + 64 * u + 8 * wave) * CK), 16, va, u * step64, 0, 0);
     }
     const auto r2 = rsrc(p.bq + n0 * Kp + kc);
 #pragma unroll
-    for (int u = 0; u < PB; ++u) rb[u] = bload(r2, voff, u * ustep);
-  };
-  // the rows a thread stages are srow + 64 u: one swizzle for all of them
-  static_assert(NT / 8 == 64, "staged rows of one thread 64 apart");
-  const int srow = tid >> 3;
-  const int aoff = lds_off(srow, tid & 7), boff = lds_off(b_slot(srow), tid & 7);
-  auto store = [&](int buf) __attribute__((always_inline)) {
-    unsigned char* st = lds + buf * STAGE;
-#pragma unroll
-    for (int a = 0; a < NA; ++a)
-#pragma unroll
-      for (int u = 0; u < PA; ++u)
-        *reinterpret_cast<v4u*>(st + (a * BM + u * (NT / 8)) * CK + aoff) = ra[a][u];
-#pragma unroll
     for (int u = 0; u < PB; ++u)
-      *reinterpret_cast<v4u*>(st + (NA * BM + u * (NT / 8)) * CK + boff) = rb[u];
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          r2, lds_ptr(st + (NA * BM + 64 * u + 8 * wave) * CK), 16, vb, u * step64, 0, 0);
   };
 
   v4f acc[FM][FN];
@@ -435,8 +436,7 @@ __global__ __launch_bounds__(wide8::NT, 1) void coded_gemm_fp8_wide_kernel(Fp8Pa
   const int64_t np128 = p.Np / 128;
 
   const int x0 = lds_off(c16, 2 * q) - c16 * CK;  // fragment rows are c16 mod 16
-  auto compute = [&](int buf, int c) __attribute__((always_inline)) {
-    const unsigned char* st = lds + buf * STAGE;
+  auto compute = [&](const unsigned char* st, int c) __attribute__((always_inline)) {
     const float s = sa[c] * sbp[(int64_t)c * np128];
     v8i a[NA][FM];
 #pragma unroll
@@ -464,17 +464,26 @@ __global__ __launch_bounds__(wide8::NT, 1) void coded_gemm_fp8_wide_kernel(Fp8Pa
     }
   };
 
+  // Chunk c sits in stage c & 1.  A stage is refilled only after the
+  // barrier that ends the chunk before it, and each chunk ends with this
+  // wave's loads done (vmcnt 0) and a barrier, so every wave's part of the
+  // next stage has landed before any wave reads it.
   const int nc = (int)(Kp / CK);
-  load(0);
-  store(0);
+  dma(lds0, 0);
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  for (int c = 0; c + 1 < nc; ++c) {
-    load(c + 1);
-    compute(c & 1, c);
-    store((c + 1) & 1);
+  for (int c = 0; c < nc; c += 2) {
+    if (c + 1 < nc) dma(lds1, c + 1);
+    compute(lds0, c);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    if (c + 1 < nc) {
+      if (c + 2 < nc) dma(lds0, c + 2);
+      compute(lds1, c + 1);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+    }
   }
-  compute((nc - 1) & 1, nc - 1);
 
   // The wave's rows lie in one 128-row block, hence in one symbol.
   const int64_t wrow = m0 + wm * TM;
