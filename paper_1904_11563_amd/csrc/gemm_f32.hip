@@ -597,7 +597,7 @@ constexpr int32_t kWideTile = 4;
 int32_t gemm_tile_count() { return (int32_t)(sizeof(kTiles) / sizeof(kTiles[0])); }
 TileShape gemm_tile_shape(int32_t t) { return kTiles[t].shape; }
 
-static int num_cus() {
+int device_cu_count() {
   static int cached[64] = {0};
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
@@ -622,7 +622,7 @@ hipError_t launch_coded_gemm(const GemmParams& p0, int32_t tile, hipStream_t str
     const bool fits = p.Mb % 256 == 0 && p.N % 256 == 0 && p.K % 32 == 0 &&
                       p.M % p.Mb == 0 && p.ldc % 4 == 0;
     const int64_t T = fits ? (int64_t)p.n_sym * (p.Mb / 256) * (p.N / 256) : 0;
-    const int64_t S = num_cus();  // one 256 x 256 workgroup per CU
+    const int64_t S = device_cu_count();  // one 256 x 256 workgroup per CU
     // Full rounds of 256 x 256 tiles run wide; a last round under 90 % full
     // runs as 64 x 128 sub-tiles (eight per tile, several per CU), which
     // keeps every CU busy to the end.  Both kernels sum in the same order,

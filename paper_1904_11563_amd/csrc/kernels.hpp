@@ -155,6 +155,9 @@ hipError_t launch_gemm_bf16_grouped(const GroupDesc* d, const GroupTile* tiles, 
                                     hipStream_t stream);
 // Grouped peel: block b belongs to product pmap[b] and is block
 // b - pstart[pmap[b]] of that product's peel grid.
+// Compute units of the current device (cached per device; 256 if unknown).
+int device_cu_count();
+
 hipError_t launch_peel_grouped(const GroupDesc* d, const int64_t* pstart, const int32_t* pmap,
                                int64_t total_blocks, int32_t max_slots, size_t max_program,
                                hipStream_t stream);

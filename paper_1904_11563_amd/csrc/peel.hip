@@ -20,6 +20,8 @@
 // reads descriptors from LDS instead of chasing them through global memory.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace bpx {
@@ -28,7 +30,7 @@ namespace {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr int kBatch = 8;  // steps whose loads are issued together
+constexpr int kBatch = 16;  // steps whose loads are issued together (all of a 16-step program)
 
 __device__ __forceinline__ int64_t valid_rows(const PeelParams& p, int64_t base) {
   return p.M - base < p.Mb ? p.M - base : p.Mb;
@@ -109,6 +111,17 @@ __device__ __forceinline__ void peel_block(const PeelParams& p, int64_t block, f
 }
 
 // ------------------------------------------------------------- vector form --
+// Y and C are reached through pointers read from memory (the grouped form's
+// descriptors), which the compiler would access with flat instructions;
+// those count on the LDS counter as well, so every wait for an LDS read of
+// the program or a slot would also wait for the HBM loads in flight.  The
+// product buffers are device memory: accessed as global.
+typedef __attribute__((address_space(1))) v4f gv4f;
+__device__ __forceinline__ v4f gload4(const float* ptr) {
+  return *(const gv4f*)ptr;
+}
+__device__ __forceinline__ void gstore4(float* ptr, v4f v) { *(gv4f*)ptr = v; }
+
 template <int THREADS>
 __device__ __forceinline__ void peel_block4(const PeelParams& p, int64_t block, v4f* xs,
                                             const PeelStep* steps, const int32_t* subs) {
@@ -132,9 +145,9 @@ __device__ __forceinline__ void peel_block4(const PeelParams& p, int64_t block, 
         const int64_t base = (int64_t)S.s * p.Mb;
         if (r < valid_rows(p, base)) {
           if (S.src >= 0)
-            y[i] = *reinterpret_cast<const v4f*>(p.Y + (int64_t)S.src * slot_elems + r * p.N + c);
+            y[i] = gload4(p.Y + (int64_t)S.src * slot_elems + r * p.N + c);
           else
-            y[i] = *reinterpret_cast<const v4f*>(p.C + (base + r) * p.ldc + c);
+            y[i] = gload4(p.C + (base + r) * p.ldc + c);
         }
       }
     }
@@ -167,8 +180,7 @@ __device__ __forceinline__ void peel_block4(const PeelParams& p, int64_t block, 
         }
       }
       if (S.slot >= 0) xs[S.slot * THREADS + tid] = x;
-      if (S.write && active && r < valid)
-        *reinterpret_cast<v4f*>(p.C + (base + r) * p.ldc + c) = x;
+      if (S.write && active && r < valid) gstore4(p.C + (base + r) * p.ldc + c, x);
     }
   }
 }
@@ -184,18 +196,38 @@ __global__ __launch_bounds__(THREADS) void peel_kernel(PeelParams p) {
 
 // Grouped peel: block b runs product pmap[b]'s program (vector form:
 // grouped products have N a multiple of 4).
-__global__ __launch_bounds__(128) void peel_grouped_kernel(const GroupDesc* d,
-                                                           const int64_t* pstart,
-                                                           const int32_t* pmap,
-                                                           int32_t max_slots) {
-  extern __shared__ v4f xs4[];  // [max_slots][128], then the product's program
-  const int64_t b = blockIdx.x;
-  const int prod = pmap[b];
-  const PeelParams& p = d[prod].pe;
+// Persistent over the 128-column-group items of all products (item b of
+// product i is b - pstart[i], pmap[b] = i): workgroup w takes a contiguous
+// range of items, so consecutive items mostly belong to one product and its
+// step program is staged once, not per item.  An item then costs one round
+// of loads (its y values) instead of four dependent ones (item -> product ->
+// descriptor -> program -> y).  The LDS slots are per thread and rewritten
+// by each item before they are read, so items need no barrier between them;
+// a new program is staged behind a barrier.
+__global__ __launch_bounds__(128) void peel_grouped_kernel(const GroupDesc* __restrict__ d,
+                                                           const int64_t* __restrict__ pstart,
+                                                           const int32_t* __restrict__ pmap,
+                                                           int32_t max_slots, int64_t total) {
+  extern __shared__ v4f xs4[];  // [max_slots][128], then the current product's program
   int32_t* prog = reinterpret_cast<int32_t*>(xs4 + (size_t)max_slots * 128);
-  stage_program(p, prog, 128);
-  peel_block4<128>(p, b - pstart[prod], xs4, reinterpret_cast<const PeelStep*>(prog),
-                   prog + p.nsteps * (int)(sizeof(PeelStep) / 4));
+  const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+  const int64_t b0 = (int64_t)blockIdx.x * per;
+  const int64_t b1 = b0 + per < total ? b0 + per : total;
+  int cur = -1;
+  for (int64_t b = b0; b < b1; ++b) {
+    // uniform by construction; readfirstlane lets the compiler keep the
+    // descriptor in scalar registers, copied once per item (a reference
+    // would be reloaded after every store to C, which might alias it)
+    const int prod = __builtin_amdgcn_readfirstlane(pmap[b]);
+    const PeelParams p = d[prod].pe;
+    if (prod != cur) {
+      if (cur >= 0) __syncthreads();  // every thread is done with the old program
+      stage_program(p, prog, 128);
+      cur = prod;
+    }
+    peel_block4<128>(p, b - pstart[prod], xs4, reinterpret_cast<const PeelStep*>(prog),
+                     prog + p.nsteps * (int)(sizeof(PeelStep) / 4));
+  }
 }
 
 }  // namespace
@@ -206,9 +238,12 @@ hipError_t launch_peel_grouped(const GroupDesc* d, const int64_t* pstart, const 
   if (total_blocks == 0) return hipSuccess;
   const size_t lds = (size_t)max_slots * 128 * 16 + max_program;
   if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
-  if (total_blocks > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(peel_grouped_kernel, dim3((unsigned)total_blocks), dim3(128), lds, stream,
-                     d, pstart, pmap, max_slots);
+  // as many workgroups as the CUs hold at once (LDS- or wave-limited), at
+  // most one per item
+  const int64_t per_cu = std::min<int64_t>(16, (int64_t)(160 * 1024) / (int64_t)(lds ? lds : 1));
+  const int64_t grid = std::min<int64_t>(total_blocks, (int64_t)device_cu_count() * per_cu);
+  hipLaunchKernelGGL(peel_grouped_kernel, dim3((unsigned)grid), dim3(128), lds, stream, d, pstart,
+                     pmap, max_slots, total_blocks);
   return hipGetLastError();
 }
 
