@@ -390,6 +390,18 @@ constexpr int lds_elems() {
 }
 }  // namespace flat
 
+// The grouped kernel reaches a product's tables and outputs through
+// pointers read from its descriptor, which the compiler would access with
+// flat instructions; those also count on the LDS counter, so the next
+// tile's first LDS wait would wait for this tile's output stores.  They
+// are device memory: read and written as global.
+__device__ __forceinline__ int32_t gld(const int32_t* ptr) {
+  return *(const __attribute__((address_space(1))) int32_t*)ptr;
+}
+__device__ __forceinline__ void gst(float* ptr, float v) {
+  *(__attribute__((address_space(1))) float*)ptr = v;
+}
+
 template <int SPLIT>
 __device__ __forceinline__ void bf16_flat_tile(const GemmParams& p, int mt, int nt, us* lds) {
   using namespace flat;
@@ -415,15 +427,15 @@ __device__ __forceinline__ void bf16_flat_tile(const GemmParams& p, int mt, int 
     if (gr < R) {
       const int64_t si = gr / Mb;
       lr = gr - si * Mb;
-      id_off = p.syms[4 * si + 0];
-      deg = p.syms[4 * si + 1];
+      id_off = gld(p.syms + 4 * si + 0);
+      deg = gld(p.syms + 4 * si + 1);
     }
     deg_u[u] = deg;
     idoff_u[u] = id_off;
     lr_u[u] = (int)lr;
 #pragma unroll
     for (int m = 0; m < kPre; ++m)
-      off[u][m] = m < deg ? (uint32_t)((((int64_t)p.ids[id_off + m] * Mb + lr) * lda + ak) * 4)
+      off[u][m] = m < deg ? (uint32_t)((((int64_t)gld(p.ids + id_off + m) * Mb + lr) * lda + ak) * 4)
                           : 0u;
   }
   // B: chunk c -> tile row n = f / 4, k offset (f % 4) * 8, f = tid + NT c
@@ -463,8 +475,9 @@ __device__ __forceinline__ void bf16_flat_tile(const GemmParams& p, int mt, int 
 #pragma unroll
       for (int m = 1; m < kPre; ++m) sum += pre[m][u];
       for (int m = kPre; m < deg_u[u]; ++m) {  // members beyond the prefetch depth
-        const int64_t row = (int64_t)p.ids[idoff_u[u] + m] * Mb + lr_u[u];
-        if (row < M) sum += *reinterpret_cast<const v4f*>(p.A + row * lda + k0 + ak);
+        const int64_t row = (int64_t)gld(p.ids + idoff_u[u] + m) * Mb + lr_u[u];
+        if (row < M)
+          sum += *(const __attribute__((address_space(1))) v4f*)(p.A + row * lda + k0 + ak);
       }
       const v4bf hi = to_bf16(sum);
       const int ao = swz(ar + 64 * u, ak >> 3) + (ak & 7);
@@ -540,7 +553,7 @@ __device__ __forceinline__ void bf16_flat_tile(const GemmParams& p, int mt, int 
       if (gr >= R) continue;
       const int64_t si = gr / Mb;
       const int64_t lr = gr - si * Mb;
-      const int dest = p.syms[4 * si + 2];
+      const int dest = gld(p.syms + 4 * si + 2);
       float* dst;
       if (dest >= 0) {
         dst = p.Y + ((int64_t)dest * Mb + lr) * N + col0;
@@ -551,7 +564,7 @@ __device__ __forceinline__ void bf16_flat_tile(const GemmParams& p, int mt, int 
       }
 #pragma unroll
       for (int j = 0; j < FN; ++j)
-        if (col0 + 16 * j < N) dst[16 * j] = acc[i][j][r];
+        if (col0 + 16 * j < N) gst(dst + 16 * j, acc[i][j][r]);
     }
 }
 
@@ -566,16 +579,19 @@ __global__ __launch_bounds__(flat::NT, 1) void coded_gemm_bf16_flat_kernel(GemmP
 // Persistent grouped form of the flat tile (GroupTile.lin = mt * tiles_n + nt).
 template <int SPLIT>
 __global__ __launch_bounds__(flat::NT, 1) void gemm_bf16_flat_grouped_kernel(
-    const GroupDesc* d, const GroupTile* tiles, int32_t n_tiles) {
+    const GroupDesc* __restrict__ d, const GroupTile* __restrict__ tiles, int32_t n_tiles) {
   __shared__ __attribute__((aligned(16))) us lds[flat::lds_elems<SPLIT>()];
   // Each XCD takes a contiguous run of every grid-sized slice of the list,
   // so the tiles of one product (adjacent in the list) share an L2.
   const int slot = xcd_remap(blockIdx.x, gridDim.x);
   for (int t = slot; t < n_tiles; t += gridDim.x) {
-    const GroupTile gt = tiles[t];
-    const GemmParams& p = d[gt.prod].g;
-    const int mt = gt.lin / p.tiles_n;
-    bf16_flat_tile<SPLIT>(p, mt, gt.lin - mt * p.tiles_n, lds);
+    // uniform by construction; readfirstlane lets the compiler keep the
+    // descriptor in scalar registers (copied, not re-read after stores)
+    const int prod = __builtin_amdgcn_readfirstlane(tiles[t].prod);
+    const int lin = __builtin_amdgcn_readfirstlane(tiles[t].lin);
+    const GemmParams p = d[prod].g;
+    const int mt = lin / p.tiles_n;
+    bf16_flat_tile<SPLIT>(p, mt, lin - mt * p.tiles_n, lds);
     __syncthreads();  // the next tile's prologue overwrites LDS stage 0
   }
 }
