@@ -641,21 +641,39 @@ hipError_t launch_coded_gemm(const GemmParams& p0, int32_t tile, hipStream_t str
         if (err != hipSuccess) return err;
       }
       if (wide_tiles == T) return hipSuccess;
-      // Last round: split each remaining tile's K range into P pieces (as
-      // many as fill the CUs, at most 4, each at least 8 slices) when the
-      // workspace holds the partial tiles; otherwise 64 x 128 sub-tiles.
+      // Last round: split each remaining tile's K range into P pieces (2 to
+      // 4, each at least 8 slices), P chosen to minimise the rounds of
+      // pieces in units of a wide round, ceil(R P / S) / P; used when that
+      // is at most 0.8 of a round (64 x 128 sub-tiles of a 3/4-full round
+      // measured 0.86) and the workspace holds partial tiles.  The pieces
+      // run in chunks of as many tiles as the partial buffer holds, each
+      // chunk followed by its reduction; otherwise 64 x 128 sub-tiles.
       const int64_t R = T - wide_tiles;
-      int64_t P = std::min<int64_t>(4, S / R);
-      while (P > 1 && (p.K / 32) / P < 8) --P;
-      if (p.part && P >= 2 && R * P <= p.part_tiles) {
+      int64_t P = 1;
+      double best = 1e30;
+      for (int64_t q = 2; q <= 4; ++q) {
+        if ((p.K / 32) / q < 8 || !p.part || q > p.part_tiles) break;
+        const double cost = (double)((R * q + S - 1) / S) / (double)q;
+        if (cost < best - 1e-9) {
+          best = cost;
+          P = q;
+        }
+      }
+      if (P >= 2 && best <= 0.8) {
+        const int64_t chunk = p.part_tiles / P;  // tiles whose pieces fit the buffer
         p.wide_split = (int32_t)P;
-        p.wide_lin0 = (int32_t)wide_tiles;
-        hipLaunchKernelGGL(e.kernel, dim3((unsigned)(R * P)), dim3(e.threads), 0, stream, p);
-        hipError_t err = hipGetLastError();
-        if (err != hipSuccess) return err;
-        hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)(R * 64)), dim3(256), 0, stream,
-                           p);
-        return hipGetLastError();
+        for (int64_t t0 = wide_tiles; t0 < T; t0 += chunk) {
+          const int64_t r = std::min<int64_t>(chunk, T - t0);
+          p.wide_lin0 = (int32_t)t0;
+          hipLaunchKernelGGL(e.kernel, dim3((unsigned)(r * P)), dim3(e.threads), 0, stream, p);
+          hipError_t err = hipGetLastError();
+          if (err != hipSuccess) return err;
+          hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)(r * 64)), dim3(256), 0,
+                             stream, p);
+          err = hipGetLastError();
+          if (err != hipSuccess) return err;
+        }
+        return hipSuccess;
       }
       const TileEntry& s = kTiles[1];
       p.wide_rem = 1;

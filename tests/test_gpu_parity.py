@@ -419,6 +419,37 @@ def test_wide_tile_split_k_last_round():
     assert relf(Cw, Af.astype(np.float64) @ Bf.astype(np.float64)) <= TOL_F32
 
 
+def test_wide_tile_split_k_chunked_last_round():
+    """A last round of more than half the CUs: 12 symbols x 37 column tiles
+    = 444 tiles, so on a 256-CU MI355X one full round and 188 tiles split
+    four ways (three rounds of quarter pieces), run in chunks of 64 tiles
+    that fit the 256-tile partial buffer (the last chunk ragged), each chunk
+    reduced in piece order.  Integer operands decode exactly, floats agree
+    with the 64 x 128 tiling to the FP32 summation-order level, and two runs
+    are bit-identical."""
+    code = code642()
+    M, K, N = 2048, 1024, 37 * 256
+    plan = bpx.Plan(code, list(range(6)), 0, bpx.MODE_FULL, M, K, N)
+    A = inputs.integers(9, inputs.TAG_A, (M, K))
+    B = inputs.integers(9, inputs.TAG_B, (K, N))
+    Af = inputs.normal(9, inputs.TAG_A, (M, K))
+    Bf = inputs.normal(9, inputs.TAG_B, (K, N))
+    try:
+        bpx.force_tile(6)
+        _say("wide chunked split-K integer")
+        C = run(plan, A, B)
+        assert np.array_equal(C.astype(np.float64), A.astype(np.float64) @ B.astype(np.float64))
+        Cw = run(plan, Af, Bf)
+        Cw2 = run(plan, Af, Bf)
+        bpx.force_tile(1)
+        C1 = run(plan, Af, Bf)
+    finally:
+        bpx.force_tile(-1)
+    assert np.array_equal(Cw, Cw2)
+    assert relf(Cw, C1) <= 1e-6
+    assert relf(Cw, Af.astype(np.float64) @ Bf.astype(np.float64)) <= TOL_F32
+
+
 def test_wide_tile_exact_and_identical_to_small_tile():
     """The 256 x 256 FP32 tiles (three wave layouts) on a shape that fills
     more than one round of the CUs, whose last round (K = 96: too few
