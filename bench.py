@@ -257,7 +257,10 @@ def run_single(args):
         gemm_flops = 2.0 * Mb * w.K * Nb * passes
     achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12
     if two_d:
-        f32_kernel = "coded_gemm_2d_kernel (64x128 tiles of block products)"
+        full = Mb % 256 == 0 and Nb % 256 == 0 and w.K % 32 == 0 and grid * Mb == w.M
+        f32_kernel = ("coded_gemm_2d_wide_kernel (256x256 tiles of block products, symbols "
+                      "dealt by decreasing passes)" if full else
+                      "coded_gemm_2d_kernel (64x128 tiles of block products)")
     elif Mb % 256 == 0 and w.N % 256 == 0 and w.K % 32 == 0 and w.M % Mb == 0:
         f32_kernel = ("coded_gemm_f32_wide_kernel<4,2> (full rounds of 256x256 tiles; a short "
                       "last round split along K + splitk_reduce_kernel, or as "

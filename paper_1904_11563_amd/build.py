@@ -21,10 +21,13 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function"]
 # Per-source extras: the iterative ILP scheduler interleaves LDS reads and
-# MFMAs better in the FP32 / BF16 GEMM loops (measured); it is not used on
-# the FP8 source, where this compiler version fails with it.
+# MFMAs better in the FP32 / BF16 GEMM loops (measured), and keeps the
+# two-dimensional form's 256 x 256 kernel within its registers (the default
+# scheduler spills it); it is not used on the FP8 source, where this
+# compiler version fails with it.
 EXTRA = {"gemm_f32.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
-         "gemm_bf16.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"]}
+         "gemm_bf16.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
+         "gemm2d.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"]}
 
 
 def sources():

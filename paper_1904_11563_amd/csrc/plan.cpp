@@ -200,10 +200,31 @@ int make_plan(const bpx_code& code, const int32_t* arrival, int32_t n_arrival, i
     plan->dest.push_back(d);
   }
 
-  // GEMM symbol table.
+  // GEMM symbol table.  In the two-dimensional form a gray symbol costs one
+  // pass over K per member, the others one pass; the table lists the
+  // symbols by decreasing passes (stable), so that a launch deals the
+  // longest tiles out first.
   plan->gemm_syms.clear();
   plan->gemm_ids.clear();
-  for (size_t i = 0; i < plan->computed.size(); ++i) {
+  std::vector<size_t> gorder(plan->computed.size());
+  std::iota(gorder.begin(), gorder.end(), (size_t)0);
+  if (plan->grid > 1) {
+    const int32_t G = plan->grid;
+    std::vector<int32_t> passes(plan->computed.size(), 1);
+    for (size_t i = 0; i < plan->computed.size(); ++i) {
+      const int32_t g = plan->computed[i];
+      const int32_t b = code.sym_ptr[g], e = code.sym_ptr[g + 1];
+      bool same_r = true, same_c = true;
+      for (int32_t t = b + 1; t < e; ++t) {
+        same_r = same_r && code.sym_data[t] / G == code.sym_data[b] / G;
+        same_c = same_c && code.sym_data[t] % G == code.sym_data[b] % G;
+      }
+      if (!same_r && !same_c) passes[i] = e - b;
+    }
+    std::stable_sort(gorder.begin(), gorder.end(),
+                     [&](size_t x, size_t y) { return passes[x] > passes[y]; });
+  }
+  for (size_t i : gorder) {
     const int32_t g = plan->computed[i];
     plan->gemm_syms.push_back((int32_t)plan->gemm_ids.size());
     plan->gemm_syms.push_back(code.deg(g));

@@ -304,6 +304,52 @@ def test_two_dimensional_form_exact_and_products():
                 assert np.array_equal(got, want[g][:rows]), g
 
 
+def test_two_dimensional_wide_tiles_exact_and_products():
+    """The two-dimensional form on full 256-multiple blocks, which run on the
+    256 x 256 tiling: the (12,8,2) searched code over its 4 x 4 grid (gray
+    symbols, symbols sharing an A block and symbols sharing a B block all
+    present), one and four tiles per product.  Every coded product equals
+    the oracle's exactly on integer operands, straggler arrivals decode to
+    A.B exactly, and float operands stay within the FP32 bound."""
+    from oracle import pipeline2d
+    code = lib_code(inputs.CODE_1282)
+    oc = oracle_of(code)
+    sym = {g: d for g, _, d in oc.symbols()}
+    for M, K, N in ((1024, 96, 1024), (2048, 96, 2048)):
+        A = inputs.integers(52, inputs.TAG_A, (M, K))
+        B = inputs.integers(52, inputs.TAG_B, (K, N))
+        plan = bpx.Plan(code, list(range(12)), 0, bpx.MODE_FULL, M, K, N, two_d=True)
+        grid, Nb = plan.grid()
+        Mb = plan.info()["Mb"]
+        assert Mb % 256 == 0 and Nb % 256 == 0 and grid * Mb == M and grid * Nb == N
+        sch = plan.schedule()
+        kinds = {pipeline2d.kind(sym[g], grid) for g in sch["computed"].tolist()}
+        assert {"a", "b", "gray"} <= kinds
+        _say("2-D wide products", M, K, N)
+        Cd = torch.zeros((M, N), device="cuda")
+        ws = bpx.alloc_workspace(plan)
+        bpx.coded_gemm(plan, dev(A), dev(B), Cd, ws)
+        Y = host(ws).view(np.float32)
+        C = host(Cd)
+        want = pipeline2d.coded_products(A, B, oc, sch["computed"].tolist())
+        for g, d in zip(sch["computed"].tolist(), sch["dest"].tolist()):
+            if d >= 0:
+                got = Y[d * Mb * Nb:(d + 1) * Mb * Nb].reshape(Mb, Nb).astype(np.float64)
+            else:
+                r, c = divmod(-1 - d, grid)
+                got = C[r * Mb:(r + 1) * Mb, c * Nb:(c + 1) * Nb].astype(np.float64)
+            assert np.array_equal(got, want[g]), (g, pipeline2d.kind(sym[g], grid))
+        R = A.astype(np.float64) @ B.astype(np.float64)
+        Af = inputs.normal(53, inputs.TAG_A, (M, K))
+        Bf = inputs.normal(53, inputs.TAG_B, (K, N))
+        for seed in range(2):
+            arrival, _ = inputs.shifted_exp_arrival(seed, 12)
+            sp = bpx.Plan(code, arrival, 0, bpx.MODE_STRAGGLER, M, K, N, two_d=True)
+            _say("2-D wide straggler", M, seed)
+            assert np.array_equal(run(sp, A, B).astype(np.float64), R), seed
+            assert relf(run(sp, Af, Bf), pipeline.uncoded(Af, Bf)) <= TOL_F32
+
+
 def test_two_dimensional_form_float_tolerance():
     """The (12,8,2) searched code in the two-dimensional form (4 x 4 block
     grid, gray symbols present) on float operands: relative Frobenius error
