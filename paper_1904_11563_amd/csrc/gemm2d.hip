@@ -307,11 +307,24 @@ __global__ __launch_bounds__(w2d::NT, 1) void coded_gemm_2d_wide_kernel(GemmPara
   // decreasing passes) with no XCD remapping: workgroups are dealt to the
   // XCDs round-robin, so every XCD gets its share of the longest tiles
   // first.  (Contiguous XCD ranges put all the gray symbols' tiles on a
-  // few XCDs and left the others idle: 37.9 ms against 20 ms.)
+  // few XCDs and left the others idle: 37.9 ms against 23.1 ms.)
+  // Within a symbol, the tile dealt to XCD x as its u-th is the
+  // (x per/8 + u)-th of the symbol's tiles in row-pair order (two row panels
+  // at a time, walking the columns), so an XCD's tiles of a symbol form a
+  // compact 2 x (per/16) block sharing A and B panels in its L2.
   const int per_sym = p.tiles_m * p.tiles_n;
   const int si = (int)blockIdx.x / per_sym;
-  const int rem = (int)blockIdx.x - si * per_sym;
-  const int mt = rem / p.tiles_n, nt = rem - mt * p.tiles_n;
+  int rem = (int)blockIdx.x - si * per_sym;
+  if ((per_sym & 7) == 0) rem = (rem & 7) * (per_sym >> 3) + (rem >> 3);
+  int mt, nt;
+  {
+    const int pg = 2 * p.tiles_n;  // tiles per row pair
+    const int g = rem / pg, first = 2 * g;
+    const int gsz = p.tiles_m - first < 2 ? p.tiles_m - first : 2;
+    const int r = rem - g * pg;
+    mt = first + r % gsz;
+    nt = r / gsz;
+  }
   const int64_t m0 = (int64_t)mt * BM, n0 = (int64_t)nt * BN;
   const int id_off = p.syms[4 * si + 0];
   const int deg = p.syms[4 * si + 1];
