@@ -166,7 +166,11 @@ bpx_status bpx_plan_create(const bpx_code* code, const int32_t* arrival, int32_t
  * FP32 only; needs K % 4 == 0 and N a multiple of 4*grid
  * (BPX_E_UNSUPPORTED otherwise), k*b a perfect square >= 4 (BPX_E_INVALID).
  * Prefix, schedule and error behaviour as bpx_plan_create; Y slots are
- * Mb x Nb.  bpx_encode and grouped launches do not take such plans. */
+ * Mb x Nb.  Full blocks (Mb and Nb multiples of 256, M = grid*Mb, N =
+ * grid*Nb, K a multiple of 32) run on 256x256 tiles when the FP32 tile
+ * shape is one of the 256x256 ones (the default), other shapes and calls on
+ * 64x128 tiles; both sum every product in the same order (identical
+ * results).  bpx_encode and grouped launches do not take such plans. */
 bpx_status bpx_plan_create2d(const bpx_code* code, const int32_t* arrival, int32_t n_arrival,
                              int32_t n_lost, int32_t mode, int64_t M, int64_t K, int64_t N,
                              int32_t prec, bpx_plan** out);
@@ -313,8 +317,10 @@ bpx_status bpx_coded_matmul_grouped(bpx_plan* const* plans, const float* const* 
  * with 2x2, 2x4 and 4x2 waves (the default), used when Mb and N are
  * multiples of 256, K of 32 and every data block is full, otherwise the call
  * takes shape 1; a last round of 256x256 tiles under 90% of the CUs runs as
- * pieces of its K range (up to 4, summed in piece order by a second kernel)
- * when the workspace holds the partial tiles, else as 64x128 sub-tiles.
+ * 2 to 4 pieces of each tile's K range (summed in piece order by a second
+ * kernel; run in chunks that fit the workspace's partial tiles) when that
+ * takes at most 0.8 of a round and the workspace holds partial tiles, else
+ * as 64x128 sub-tiles.
  * Results are deterministic; shapes and the split change only the FP32
  * summation order.  FP8 / FP8x2: shape 0 is one 128x128 tile grid per
  * symbol, shape 1 (the default) one grid of 128x256 tiles over all symbols'

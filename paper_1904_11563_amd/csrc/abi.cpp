@@ -168,7 +168,7 @@ bpx_status gemm_impl(bpx_plan* plan, const float* A, int64_t lda, const float* B
   if (plan->grid > 1) {
     p.grid = plan->grid;
     p.Nb = plan->Nb;
-    e = launch_coded_gemm_2d(p, stream);
+    e = launch_coded_gemm_2d(p, tile, stream);
     if (e == hipErrorInvalidValue)
       return fail(BPX_E_UNSUPPORTED, "block too large for 32-bit buffer offsets");
   } else if (plan->is_fp8()) {

@@ -514,13 +514,13 @@ __global__ __launch_bounds__(w2d::NT, 1) void coded_gemm_2d_wide_kernel(GemmPara
 
 }  // namespace
 
-hipError_t launch_coded_gemm_2d(const GemmParams& p0, hipStream_t stream) {
+hipError_t launch_coded_gemm_2d(const GemmParams& p0, int32_t tile, hipStream_t stream) {
   GemmParams p = p0;
   // buffer ranges and offsets are 32-bit
   const int64_t lim = (int64_t)1 << 31;
   if ((p.Mb + BM) * p.lda * 4 >= lim || p.K * p.ldb * 4 >= lim) return hipErrorInvalidValue;
   // 256 x 256 tiles where every block is full and the shapes divide
-  const bool wide = p.Mb % 256 == 0 && p.Nb % 256 == 0 && p.K % 32 == 0 &&
+  const bool wide = tile >= 4 && p.Mb % 256 == 0 && p.Nb % 256 == 0 && p.K % 32 == 0 &&
                     p.M == (int64_t)p.grid * p.Mb && p.N == (int64_t)p.grid * p.Nb &&
                     p.ldc % 4 == 0 && p.Nb % 4 == 0;
   if (wide) {

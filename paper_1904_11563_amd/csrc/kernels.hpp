@@ -118,7 +118,9 @@ TileShape gemm_tile_shape(int32_t t);
 
 hipError_t launch_coded_gemm(const GemmParams& p, int32_t tile, hipStream_t stream);
 // FP32 coded GEMM of the two-dimensional form (64 x 128 tiles).
-hipError_t launch_coded_gemm_2d(const GemmParams& p, hipStream_t stream);
+// tile: the FP32 tile shape chosen for the call; the 256 x 256 shapes (4-6)
+// take the wide 2-D kernel where the blocks allow it, others 64 x 128.
+hipError_t launch_coded_gemm_2d(const GemmParams& p, int32_t tile, hipStream_t stream);
 
 int32_t bf16_tile_count();
 TileShape bf16_tile_shape(int32_t t);

@@ -347,7 +347,14 @@ def test_two_dimensional_wide_tiles_exact_and_products():
             sp = bpx.Plan(code, arrival, 0, bpx.MODE_STRAGGLER, M, K, N, two_d=True)
             _say("2-D wide straggler", M, seed)
             assert np.array_equal(run(sp, A, B).astype(np.float64), R), seed
-            assert relf(run(sp, Af, Bf), pipeline.uncoded(Af, Bf)) <= TOL_F32
+            Cw = run(sp, Af, Bf)
+            assert relf(Cw, pipeline.uncoded(Af, Bf)) <= TOL_F32
+            try:  # the 64 x 128 tiling sums every product in the same order
+                bpx.force_tile(1)
+                C1 = run(sp, Af, Bf)
+            finally:
+                bpx.force_tile(-1)
+            assert np.array_equal(Cw, C1), seed
 
 
 def test_two_dimensional_form_float_tolerance():
