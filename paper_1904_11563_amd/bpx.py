@@ -42,7 +42,7 @@ MODE_NAMES = {"erasure": MODE_ERASURE, "straggler": MODE_STRAGGLER,
 EXPORTS = [
     "bpx_code_build", "bpx_code_from_csr", "bpx_code_info", "bpx_code_csr", "bpx_code_free",
     "bpx_plan_create", "bpx_plan_create2d", "bpx_plan_grid", "bpx_plan_info",
-    "bpx_plan_schedule", "bpx_plan_workspace_bytes",
+    "bpx_plan_schedule", "bpx_plan_peel_program", "bpx_plan_workspace_bytes",
     "bpx_plan_workspace_layout",
     "bpx_plan_upload", "bpx_plan_free", "bpx_encode", "bpx_coded_gemm", "bpx_peel_decode",
     "bpx_coded_matmul", "bpx_coded_matmul_grouped", "bpx_group_workspace_bytes",
@@ -77,6 +77,8 @@ _sig = {
     "bpx_plan_info": (C.c_int, [_p] + [_i32p] * 5 + [C.POINTER(C.c_int64)]),
     "bpx_plan_schedule": (C.c_int, [_p] + [C.POINTER(_i32p)] * 5 + [C.POINTER(_u16p),
                                                                     C.POINTER(_i32p)]),
+    "bpx_plan_peel_program": (C.c_int, [_p, C.POINTER(_i32p), _i32p, _i32p, C.POINTER(_i32p),
+                                        _i32p, _i32p]),
     "bpx_plan_workspace_bytes": (C.c_int, [_p, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
     "bpx_plan_workspace_layout": (C.c_int, [_p, C.POINTER(C.c_size_t), C.c_int32]),
     "bpx_plan_upload": (C.c_int, [_p]),
@@ -272,6 +274,20 @@ class Plan:
             "sub_data": arr(sd, int(sub_ptr[-1]), np.uint16),
             "unrecovered": arr(ptrs[5], inf["n_unrecovered"]),
         }
+
+    PEEL_FIELDS = ("s", "src", "nsub", "sub_off", "f64", "slot", "write", "brow", "bcol")
+
+    def peel_program(self):
+        """The decode's step program: {"steps": int32 [n_steps, 9] in
+        PEEL_FIELDS order, "subs": the subtrahends' LDS slots, "n_slots"}."""
+        st, sb = _i32p(), _i32p()
+        n, w, ns, nsl = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(_lib.bpx_plan_peel_program(self._h, C.byref(st), C.byref(n), C.byref(w),
+                                          C.byref(sb), C.byref(ns), C.byref(nsl)))
+        steps = (np.ctypeslib.as_array(st, shape=(n.value * w.value,)).copy().reshape(n.value, w.value)
+                 if n.value else np.zeros((0, 9), np.int32))
+        subs = np.ctypeslib.as_array(sb, shape=(ns.value,)).copy() if ns.value else np.zeros(0, np.int32)
+        return {"steps": steps, "subs": subs, "n_slots": nsl.value}
 
     def workspace_bytes(self):
         ws, enc = C.c_size_t(), C.c_size_t()

@@ -638,6 +638,20 @@ bpx_status bpx_plan_schedule(const bpx_plan* plan, const int32_t** computed, con
   return BPX_OK;
 }
 
+bpx_status bpx_plan_peel_program(const bpx_plan* plan, const int32_t** steps, int32_t* n_steps,
+                                 int32_t* step_words, const int32_t** subs, int32_t* n_subs,
+                                 int32_t* n_slots) {
+  if (!plan) return fail(BPX_E_INVALID, "null plan");
+  static_assert(sizeof(PeelStep) == 9 * sizeof(int32_t), "peel step record");
+  if (steps) *steps = reinterpret_cast<const int32_t*>(plan->steps.data());
+  if (n_steps) *n_steps = (int32_t)plan->steps.size();
+  if (step_words) *step_words = (int32_t)(sizeof(PeelStep) / sizeof(int32_t));
+  if (subs) *subs = plan->step_subs.data();
+  if (n_subs) *n_subs = (int32_t)plan->step_subs.size();
+  if (n_slots) *n_slots = plan->n_lds_slots;
+  return BPX_OK;
+}
+
 bpx_status bpx_plan_workspace_bytes(const bpx_plan* plan, size_t* ws_bytes,
                                     size_t* encode_bytes) {
   if (!plan) return fail(BPX_E_INVALID, "null plan");

@@ -8,6 +8,7 @@
 // count of its unknown ids and the XOR of those ids, so a count of one names
 // the id directly.
 #include <algorithm>
+#include <functional>
 #include <numeric>
 
 #include "host.hpp"
@@ -248,9 +249,37 @@ int make_plan(const bpx_code& code, const int32_t* arrival, int32_t n_arrival, i
     });
     std::vector<char> used(kb, 0);
     for (uint16_t u : plan->sub_data) used[u] = 1;
-    std::vector<int32_t> slot(kb, -1);
+    // LDS slots by liveness: a block's slot is taken when it is recovered
+    // and freed after the last step that subtracts it (that step reads its
+    // subtrahends before it writes its own result, so it may reuse one of
+    // their slots); the lowest free slot is taken first.  The peel kernels'
+    // LDS, and with it how many workgroups a CU holds, scale with the count.
+    std::vector<int32_t> pos(kb, -1), last_use(kb, -1);
+    for (size_t i = 0; i < order.size(); ++i) pos[order[i]] = (int32_t)i;
     for (int32_t s = 0; s < kb; ++s)
-      if (used[s]) slot[s] = plan->n_lds_slots++;
+      for (int32_t e = plan->sub_ptr[s]; e < plan->sub_ptr[s + 1]; ++e)
+        last_use[plan->sub_data[e]] = std::max(last_use[plan->sub_data[e]], pos[s]);
+    std::vector<int32_t> slot(kb, -1);
+    {
+      std::vector<int32_t> free_slots;  // kept sorted descending: back() is the lowest
+      for (size_t i = 0; i < order.size(); ++i) {
+        const int32_t s = order[i];
+        for (int32_t e = plan->sub_ptr[s]; e < plan->sub_ptr[s + 1]; ++e) {
+          const int32_t u = plan->sub_data[e];
+          if (last_use[u] == (int32_t)i && slot[u] >= 0) {
+            free_slots.push_back(slot[u]);
+            std::sort(free_slots.begin(), free_slots.end(), std::greater<int32_t>());
+          }
+        }
+        if (!used[s]) continue;
+        if (!free_slots.empty()) {
+          slot[s] = free_slots.back();
+          free_slots.pop_back();
+        } else {
+          slot[s] = plan->n_lds_slots++;
+        }
+      }
+    }
     auto dest_of = [&](int32_t g) {
       auto it = std::lower_bound(plan->computed.begin(), plan->computed.end(), g);
       return plan->dest[it - plan->computed.begin()];
