@@ -449,18 +449,27 @@ __global__ __launch_bounds__(wide8::NT, 1) void coded_gemm_fp8_wide_kernel(Fp8Pa
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj)  // output column jg 64 + 4 c16 + jj, at row 16 jj + c16
         b[jj] = frag(st + (NA * BM + wn * TN + jg * 64 + 16 * jj + c16) * CK, x0);
+      // Per fragment row: the four residual-plane products first, then the
+      // four main-plane products accumulating onto them, so that no MFMA
+      // waits on the one just issued (same sums in the same order).
 #pragma unroll
-      for (int i = 0; i < FM; ++i)
+      for (int i = 0; i < FM; ++i) {
+        v4f part[4];
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
-          v4f part = {0.f, 0.f, 0.f, 0.f};
+          part[jj] = v4f{0.f, 0.f, 0.f, 0.f};
           if (X2)  // residual plane, E8M0 scale 2^-4
-            part = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[1][i], b[jj], part, 0, 0,
-                                                                     0, 123, 0, 127);
-          part = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[0][i], b[jj], part, 0, 0, 0,
-                                                                   127, 0, 127);
-          acc[i][jg * 4 + jj] += s * part;
+            part[jj] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[NA - 1][i], b[jj],
+                                                                         part[jj], 0, 0, 0, 123, 0,
+                                                                         127);
         }
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+          part[jj] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[0][i], b[jj], part[jj], 0,
+                                                                       0, 0, 127, 0, 127);
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) acc[i][jg * 4 + jj] += s * part[jj];
+      }
     }
   };
 
