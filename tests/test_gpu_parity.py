@@ -443,6 +443,27 @@ def test_fp32_scale_full_size_sampled():
     assert np.isfinite(C).all()
 
 
+def test_fp32_2d_full_size_sampled():
+    """The two-dimensional workload at the bench's size and launch (8192^3,
+    (12,8,2) code over the 4 x 4 block grid, shifted-exponential arrivals,
+    256 x 256 tiles dealt by decreasing passes): 16 sampled rows (4 per row
+    block) against float64 within the FP32 bound, everything finite."""
+    w = inputs.WORKLOADS["fp32_2d"]
+    A, B = inputs.operands(w, seed=0)
+    arrival, lost, _ = inputs.arrival_of(w, seed=0)
+    code = lib_code(w.code)
+    plan = bpx.Plan(code, arrival, lost, bpx.MODE_STRAGGLER, w.M, w.K, w.N, two_d=True)
+    _say("fp32_2d plan", plan.info())
+    C = run(plan, A, B)
+    Mb = plan.info()["Mb"]
+    rows = np.concatenate([np.arange(r * Mb + 5, (r + 1) * Mb, Mb // 4)[:4] for r in range(4)])
+    R = A[rows].astype(np.float64) @ B.astype(np.float64)
+    e = relf(C[rows], R)
+    _say("fp32_2d sampled relF", e)
+    assert e <= TOL_F32
+    assert np.isfinite(C).all()
+
+
 def test_wide_tile_split_k_last_round():
     """The 256 x 256 FP32 tiling on a shape with one full round and a short
     last round (12 symbols x 24 column tiles = 288 tiles; K = 1024 gives the
@@ -873,6 +894,45 @@ def test_grouped_integer_exact_and_float_tolerance():
             _say("grouped bf16x3 per-product (i, depth, relF)", errs)
             _say("grouped bf16x3 batch relF", np.sqrt(num / den))
             assert np.sqrt(num / den) <= TOL_BF16X3
+
+
+def test_batch_full_size_sampled():
+    """The bench's batch at full size: 256 products (M, K, N log-uniform in
+    [256, 4096]), codes (6,4,2) and (12,8,2) with their own seeded erasures,
+    BF16x3, one grouped launch (persistent GEMM and peel over all
+    products).  Four sampled rows of every product against float64: the
+    whole sample within the BF16x3 bound, each product within sqrt(2 d) of
+    it (d its deepest release round)."""
+    codes_by_k = {4: code642(), 8: lib_code(inputs.CODE_1282)}
+    shapes = inputs.batch_shapes(0, 256)
+    plans, As, Bs, Cs, samples = [], [], [], [], []
+    for i, (M, K, N, k) in enumerate(shapes):
+        code = codes_by_k[k]
+        n = code.info()["n"]
+        arrival, _ = inputs.erasure_arrival(i, n, n - k)
+        plans.append(bpx.Plan(code, arrival, 0, bpx.MODE_STRAGGLER, M, K, N, bpx.PREC_BF16X3))
+        g = torch.Generator(device="cuda").manual_seed(1000 + i)
+        As.append(torch.randn(M, K, device="cuda", generator=g))
+        Bs.append(torch.randn(K, N, device="cuda", generator=g))
+        Cs.append(torch.full((M, N), float("nan"), device="cuda"))
+        samples.append(np.linspace(0, M - 1, 4).astype(np.int64))
+    ws = torch.empty(bpx.group_workspace_bytes(plans), dtype=torch.uint8, device="cuda")
+    _say("batch full size: products", len(plans))
+    grp = bpx.Group(plans, As, Bs, Cs, ws)
+    grp.launch()
+    torch.cuda.synchronize()
+    num = den = 0.0
+    for i, rows in enumerate(samples):
+        r = torch.from_numpy(rows).cuda()
+        Cr = Cs[i].index_select(0, r).cpu().numpy().astype(np.float64)
+        R = (As[i].index_select(0, r).cpu().double() @ Bs[i].cpu().double()).numpy()
+        assert np.isfinite(Cr).all(), i
+        d = plans[i].info()["depth_max"]
+        assert relf(Cr, R) <= TOL_BF16X3 * np.sqrt(2 * max(d, 1)), (i, d)
+        num += float(np.sum((Cr - R) ** 2))
+        den += float(np.sum(R ** 2))
+    _say("batch full size sampled relF", np.sqrt(num / den))
+    assert np.sqrt(num / den) <= TOL_BF16X3
 
 
 def test_grouped_graph_replay_matches_eager():
