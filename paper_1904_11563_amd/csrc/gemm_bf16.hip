@@ -347,9 +347,10 @@ __device__ __forceinline__ void bf16_tile(const GemmParams& p, int si, int mt, i
 // small blocks waste no rows.  Each thread looks up the symbol and member
 // rows of the two A rows it stages; the encode sums the members in FP32 and
 // splits the sum into BF16 hi / lo while staging.  8 waves (2 x 4) of
-// 64 x 64, K-stages of 32, the next stage's loads in registers during the
-// current stage's MFMAs, LDS double buffer.  Rows past a product's end and B
-// rows past N come back as zeros from the buffer resources' range check.
+// 64 x 64, K-stages of 32, LDS double buffer: during the current stage's
+// MFMAs the next stage's A loads land in registers and its B loads go
+// straight to LDS.  Rows past a product's end come back as zeros from the
+// buffer resource's range check.
 // Needs K a multiple of 32.  Output columns are not interleaved here (B is
 // stored n-major, and interleaved columns would read rows four apart, which
 // no row swizzle spreads over the banks).
@@ -371,7 +372,6 @@ constexpr int A_PLANE = BM * FKS, B_PLANE = BN * FKS;
 constexpr int UA = BM * BK / 4 / NT;        // float4 of A per thread per member (2)
 constexpr int UB = BN * BK * 2 / 16 / NT;   // 16-byte B chunks per thread per plane (2)
 constexpr int kRsrcWord3 = 0x00020000;      // gfx9 raw buffer, 32-bit elements
-typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base, int64_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0,
@@ -380,14 +380,19 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base, int64_t
 __device__ __forceinline__ v4f bload(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
   return __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, 0, 0));
 }
-__device__ __forceinline__ v4u bload_u(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
-  return __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, 0, 0));
-}
 
+// A's two stages in one array; B's stages in one array each, since they are
+// filled by direct loads to LDS, and the compiler then sees that the stage
+// being filled is not the one being read (no wait on those loads there).
 template <int SPLIT>
-constexpr int lds_elems() {
-  return 2 * (SPLIT == 3 ? 2 : 1) * (A_PLANE + B_PLANE);
+constexpr int a_elems() {
+  return 2 * (SPLIT == 3 ? 2 : 1) * A_PLANE;
 }
+template <int SPLIT>
+constexpr int b_elems() {
+  return (SPLIT == 3 ? 2 : 1) * B_PLANE;
+}
+typedef __attribute__((address_space(3))) void* lds_addr;
 }  // namespace flat
 
 // The grouped kernel reaches a product's tables and outputs through
@@ -403,10 +408,11 @@ __device__ __forceinline__ void gst(float* ptr, float v) {
 }
 
 template <int SPLIT>
-__device__ __forceinline__ void bf16_flat_tile(const GemmParams& p, int mt, int nt, us* lds) {
+__device__ __forceinline__ void bf16_flat_tile(const GemmParams& p, int mt, int nt, us* lds_a,
+                                               us* lds_b0, us* lds_b1) {
   using namespace flat;
   constexpr int NPL = SPLIT == 3 ? 2 : 1;
-  constexpr int STAGE = NPL * (A_PLANE + B_PLANE);
+  constexpr int A_STAGE = NPL * A_PLANE;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 2, wn = wave & 3;
@@ -438,18 +444,34 @@ __device__ __forceinline__ void bf16_flat_tile(const GemmParams& p, int mt, int 
       off[u][m] = m < deg ? (uint32_t)((((int64_t)gld(p.ids + id_off + m) * Mb + lr) * lda + ak) * 4)
                           : 0u;
   }
-  // B: chunk c -> tile row n = f / 4, k offset (f % 4) * 8, f = tid + NT c
+  // B is staged by direct loads to LDS: one instruction of a wave fills 64
+  // consecutive 16-byte LDS slots, lane l the slot base + 16 l, from the
+  // lane's own global address.  Instruction c of wave w fills tile rows
+  // 16 (w + 8 c) + l / 4, slot l % 4, which holds granule
+  // (l % 4) ^ ((l >> 3) & 2) of that row (the swizzle above, the base row
+  // being a multiple of 16).  Rows past N are out of the resource's range;
+  // they only feed output columns that are never stored.
   uint32_t boff[UB];
+  {
+    const int gb = (lane & 3) ^ ((lane >> 3) & 2);
 #pragma unroll
-  for (int c = 0; c < UB; ++c) {
-    const int f = tid + NT * c;
-    boff[c] = (uint32_t)(((n0 + (f >> 2)) * Kp + (f & 3) * 8) * 2);
+    for (int c = 0; c < UB; ++c)
+      boff[c] = (uint32_t)(((16 * (wave + 8 * c) + (lane >> 2)) * Kp + gb * 8) * 2);
   }
+  static_assert(UB * 8 * 16 == BN, "B staging covers the tile");
 
   v4f preA[kPre][UA];
-  v4u brA[NPL][UB];
-  auto load = [&](v4f (&pre)[kPre][UA], v4u (&bre)[NPL][UB], int k0)
-                  __attribute__((always_inline)) {
+  auto dma_b = [&](us* bst, int k0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int pl = 0; pl < NPL; ++pl) {
+      const auto rb = rsrc((pl == 0 ? p.bt_hi : p.bt_lo) + n0 * Kp + k0, ((N - n0) * Kp - k0) * 2);
+#pragma unroll
+      for (int c = 0; c < UB; ++c)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rb, (lds_addr)(bst + pl * B_PLANE + 16 * (wave + 8 * c) * FKS), 16, boff[c], 0, 0, 0);
+    }
+  };
+  auto load = [&](v4f (&pre)[kPre][UA], int k0) __attribute__((always_inline)) {
     const auto ra = rsrc(p.A + k0, (M * lda - k0) * 4);
 #pragma unroll
     for (int u = 0; u < UA; ++u)
@@ -459,16 +481,8 @@ __device__ __forceinline__ void bf16_flat_tile(const GemmParams& p, int mt, int 
         if (m < deg_u[u]) v = bload(ra, off[u][m]);
         pre[m][u] = v;
       }
-#pragma unroll
-    for (int pl = 0; pl < NPL; ++pl) {
-      const auto rb = rsrc((pl == 0 ? p.bt_hi : p.bt_lo) + k0, (N * Kp - k0) * 2);
-#pragma unroll
-      for (int c = 0; c < UB; ++c) bre[pl][c] = bload_u(rb, boff[c]);
-    }
   };
-  auto store = [&](v4f (&pre)[kPre][UA], v4u (&bre)[NPL][UB], int buf, int k0)
-                   __attribute__((always_inline)) {
-    us* st = lds + buf * STAGE;
+  auto store = [&](v4f (&pre)[kPre][UA], us* st, int k0) __attribute__((always_inline)) {
 #pragma unroll
     for (int u = 0; u < UA; ++u) {
       v4f sum = pre[0][u];
@@ -484,14 +498,6 @@ __device__ __forceinline__ void bf16_flat_tile(const GemmParams& p, int mt, int 
       *reinterpret_cast<v4bf*>(st + ao) = hi;
       if (SPLIT == 3) *reinterpret_cast<v4bf*>(st + A_PLANE + ao) = to_bf16(sum - from_bf16(hi));
     }
-    us* Bs = st + NPL * A_PLANE;
-#pragma unroll
-    for (int pl = 0; pl < NPL; ++pl)
-#pragma unroll
-      for (int c = 0; c < UB; ++c) {
-        const int f = tid + NT * c;
-        *reinterpret_cast<v4u*>(Bs + pl * B_PLANE + swz(f >> 2, f & 3)) = bre[pl][c];
-      }
   };
 
   v4f acc[FM][FN];
@@ -500,9 +506,7 @@ __device__ __forceinline__ void bf16_flat_tile(const GemmParams& p, int mt, int 
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
-  auto compute = [&](int buf) __attribute__((always_inline)) {
-    const us* st = lds + buf * STAGE;
-    const us* Bs = st + NPL * A_PLANE;
+  auto compute = [&](const us* st, const us* Bs) __attribute__((always_inline)) {
     v8bf ah[FM], al[FM];
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
@@ -531,16 +535,32 @@ __device__ __forceinline__ void bf16_flat_tile(const GemmParams& p, int mt, int 
     }
   };
 
-  const int nk = (int)(K / BK);
-  load(preA, brA, 0);
-  store(preA, brA, 0, 0);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
+  // Stage kt sits in A stage kt & 1 and B array kt & 1.  The next stage's
+  // A loads are issued before its B loads, so the A store waits on the A
+  // loads only; each stage ends with all of this wave's loads done and a
+  // barrier, so every wave's part of the next stage is in LDS before any
+  // wave reads it, and a stage is refilled only after that barrier.
+  auto step = [&](int kt, us* a_cur, us* a_nxt, const us* b_cur, us* b_nxt, int nk)
+                  __attribute__((always_inline)) {
     const bool more = kt + 1 < nk;
-    if (more) load(preA, brA, (kt + 1) * BK);
-    compute(kt & 1);
-    if (more) store(preA, brA, (kt + 1) & 1, (kt + 1) * BK);
+    if (more) {
+      load(preA, (kt + 1) * BK);
+      dma_b(b_nxt, (kt + 1) * BK);
+    }
+    compute(a_cur, b_cur);
+    if (more) store(preA, a_nxt, (kt + 1) * BK);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+  };
+  const int nk = (int)(K / BK);
+  load(preA, 0);
+  dma_b(lds_b0, 0);
+  store(preA, lds_a, 0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; kt += 2) {
+    step(kt, lds_a, lds_a + A_STAGE, lds_b0, lds_b1, nk);
+    if (kt + 1 < nk) step(kt + 1, lds_a + A_STAGE, lds_a, lds_b1, lds_b0, nk);
   }
 
   // epilogue: lane holds rows 4q .. 4q+3 of column 16 j + c16 of each subtile
@@ -570,17 +590,21 @@ __device__ __forceinline__ void bf16_flat_tile(const GemmParams& p, int mt, int 
 
 template <int SPLIT>
 __global__ __launch_bounds__(flat::NT, 1) void coded_gemm_bf16_flat_kernel(GemmParams p) {
-  __shared__ __attribute__((aligned(16))) us lds[flat::lds_elems<SPLIT>()];
+  __shared__ __attribute__((aligned(16))) us lds_a[flat::a_elems<SPLIT>()];
+  __shared__ __attribute__((aligned(16))) us lds_b0[flat::b_elems<SPLIT>()];
+  __shared__ __attribute__((aligned(16))) us lds_b1[flat::b_elems<SPLIT>()];
   const int lin = xcd_remap(blockIdx.x, gridDim.x);
   const int mt = lin / p.tiles_n;
-  bf16_flat_tile<SPLIT>(p, mt, lin - mt * p.tiles_n, lds);
+  bf16_flat_tile<SPLIT>(p, mt, lin - mt * p.tiles_n, lds_a, lds_b0, lds_b1);
 }
 
 // Persistent grouped form of the flat tile (GroupTile.lin = mt * tiles_n + nt).
 template <int SPLIT>
 __global__ __launch_bounds__(flat::NT, 1) void gemm_bf16_flat_grouped_kernel(
     const GroupDesc* __restrict__ d, const GroupTile* __restrict__ tiles, int32_t n_tiles) {
-  __shared__ __attribute__((aligned(16))) us lds[flat::lds_elems<SPLIT>()];
+  __shared__ __attribute__((aligned(16))) us lds_a[flat::a_elems<SPLIT>()];
+  __shared__ __attribute__((aligned(16))) us lds_b0[flat::b_elems<SPLIT>()];
+  __shared__ __attribute__((aligned(16))) us lds_b1[flat::b_elems<SPLIT>()];
   // Each XCD takes a contiguous run of every grid-sized slice of the list,
   // so the tiles of one product (adjacent in the list) share an L2.
   const int slot = xcd_remap(blockIdx.x, gridDim.x);
@@ -591,8 +615,7 @@ __global__ __launch_bounds__(flat::NT, 1) void gemm_bf16_flat_grouped_kernel(
     const int lin = __builtin_amdgcn_readfirstlane(tiles[t].lin);
     const GemmParams p = d[prod].g;
     const int mt = lin / p.tiles_n;
-    bf16_flat_tile<SPLIT>(p, mt, lin - mt * p.tiles_n, lds);
-    __syncthreads();  // the next tile's prologue overwrites LDS stage 0
+    bf16_flat_tile<SPLIT>(p, mt, lin - mt * p.tiles_n, lds_a, lds_b0, lds_b1);
   }
 }
 
