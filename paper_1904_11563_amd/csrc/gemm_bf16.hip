@@ -421,8 +421,13 @@ __device__ __forceinline__ void bf16_flat_tile(const GemmParams& p, int mt, int 
   const int64_t Mb = p.Mb, M = p.M, N = p.N, K = p.K, Kp = p.kp, lda = p.lda;
   const int64_t R = (int64_t)p.n_sym * Mb;
 
-  // A: rows ar + 64 u of the tile, k ak .. ak+3 of the stage
+  // A: rows ar + 64 u of the tile, k ak .. ak+3 of the stage.  The rows of
+  // one wave can belong to symbols of different degrees.  The wave loads
+  // member m of its rows if any of them has one (a uniform branch, bit m of
+  // need), and a row without it gets the offset M lda, past the resource's
+  // range for every stage, whose load returns zeros: no per-lane branches.
   const int ar = tid >> 3, ak = (tid & 7) * 4;
+  const uint32_t absent = (uint32_t)(M * lda * 4);
   uint32_t off[UA][kPre];
   int deg_u[UA], idoff_u[UA], lr_u[UA];
 #pragma unroll
@@ -442,7 +447,7 @@ __device__ __forceinline__ void bf16_flat_tile(const GemmParams& p, int mt, int 
 #pragma unroll
     for (int m = 0; m < kPre; ++m)
       off[u][m] = m < deg ? (uint32_t)((((int64_t)gld(p.ids + id_off + m) * Mb + lr) * lda + ak) * 4)
-                          : 0u;
+                          : absent;
   }
   // B is staged by direct loads to LDS: one instruction of a wave fills 64
   // consecutive 16-byte LDS slots, lane l the slot base + 16 l, from the
@@ -460,7 +465,20 @@ __device__ __forceinline__ void bf16_flat_tile(const GemmParams& p, int mt, int 
   }
   static_assert(UB * 8 * 16 == BN, "B staging covers the tile");
 
+  int dmax = 0;
+#pragma unroll
+  for (int u = 0; u < UA; ++u) dmax = deg_u[u] > dmax ? deg_u[u] : dmax;
+  uint32_t need = 1;  // member 0 is always loaded (zeros for rows past the end)
+#pragma unroll
+  for (int m = 1; m < kPre; ++m)
+    if (__builtin_amdgcn_ballot_w64(m < dmax) != 0) need |= 1u << m;
+
+  // a member the wave skips keeps these zeros for the whole tile
   v4f preA[kPre][UA];
+#pragma unroll
+  for (int m = 0; m < kPre; ++m)
+#pragma unroll
+    for (int u = 0; u < UA; ++u) preA[m][u] = v4f{0.f, 0.f, 0.f, 0.f};
   auto dma_b = [&](us* bst, int k0) __attribute__((always_inline)) {
 #pragma unroll
     for (int pl = 0; pl < NPL; ++pl) {
@@ -476,11 +494,8 @@ __device__ __forceinline__ void bf16_flat_tile(const GemmParams& p, int mt, int 
 #pragma unroll
     for (int u = 0; u < UA; ++u)
 #pragma unroll
-      for (int m = 0; m < kPre; ++m) {
-        v4f v = {0.f, 0.f, 0.f, 0.f};
-        if (m < deg_u[u]) v = bload(ra, off[u][m]);
-        pre[m][u] = v;
-      }
+      for (int m = 0; m < kPre; ++m)
+        if ((need >> m) & 1) pre[m][u] = bload(ra, off[u][m]);
   };
   auto store = [&](v4f (&pre)[kPre][UA], us* st, int k0) __attribute__((always_inline)) {
 #pragma unroll
