@@ -270,7 +270,8 @@ struct bpx_group {
   const bpx::GroupTile* d_tiles = nullptr;
   const int32_t* d_bmap = nullptr;  // product of each split-B block
   const int32_t* d_pmap = nullptr;  // product of each peel block
-  int64_t total_b = 0, total_p = 0;
+  const int64_t* d_wstart = nullptr;  // first peel block of each peel workgroup
+  int64_t total_b = 0, total_p = 0, peel_grid = 0;
   int32_t max_slots = 0;
   size_t max_program = 0;
   std::vector<bpx::GroupLaunch> launches;
@@ -413,7 +414,32 @@ bpx_status group_build(bpx_plan* const* plans, const float* const* A, const floa
     for (int64_t b = bstart[i]; b < bend; ++b) bmap[b] = i;
     for (int64_t b = pstart[i]; b < pend; ++b) pmap[b] = i;
   }
-  // one device block: descriptors | bstart | pstart | tiles | bmap | pmap
+  // Peel workgroup ranges: a block of product i costs its program's steps
+  // plus one (the per-block work); workgroup w of G starts at the first
+  // block whose cumulative cost reaches w T / G (T the total), so that every
+  // workgroup gets about the same number of steps.
+  const int64_t pgrid = tp > 0 ? peel_grouped_grid(tp, max_slots, max_program) : 0;
+  std::vector<int64_t> wstart(pgrid + 1, tp);
+  if (pgrid > 0) {
+    int64_t T = 0;
+    for (int32_t i = 0; i < count; ++i) {
+      const int64_t pend = i + 1 < count ? pstart[i + 1] : tp;
+      T += (pend - pstart[i]) * ((int64_t)plans[i]->steps.size() + 1);
+    }
+    int64_t w = 0, cum = 0;
+    for (int32_t i = 0; i < count && w <= pgrid; ++i) {
+      const int64_t n = (i + 1 < count ? pstart[i + 1] : tp) - pstart[i];
+      const int64_t c = (int64_t)plans[i]->steps.size() + 1;
+      while (w <= pgrid) {
+        const int64_t t = w * T / pgrid;
+        if (t >= cum + n * c) break;
+        wstart[w] = pstart[i] + (t - cum + c - 1) / c;
+        ++w;
+      }
+      cum += n * c;
+    }
+  }
+  // one device block: descriptors | bstart | pstart | tiles | bmap | pmap | wstart
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   const size_t s0 = al(desc.size() * sizeof(GroupDesc));
   const size_t s1 = al(bstart.size() * 8);
@@ -421,13 +447,15 @@ bpx_status group_build(bpx_plan* const* plans, const float* const* A, const floa
   const size_t s3 = al(std::max<size_t>(tiles.size(), 1) * sizeof(GroupTile));
   const size_t s4 = al(std::max<size_t>(bmap.size(), 1) * 4);
   const size_t s5 = al(std::max<size_t>(pmap.size(), 1) * 4);
-  std::string host(s0 + s1 + s2 + s3 + s4 + s5, '\0');
+  const size_t s6 = al(wstart.size() * 8);
+  std::string host(s0 + s1 + s2 + s3 + s4 + s5 + s6, '\0');
   std::memcpy(&host[0], desc.data(), desc.size() * sizeof(GroupDesc));
   std::memcpy(&host[s0], bstart.data(), bstart.size() * 8);
   std::memcpy(&host[s0 + s1], pstart.data(), pstart.size() * 8);
   std::memcpy(&host[s0 + s1 + s2], tiles.data(), tiles.size() * sizeof(GroupTile));
   std::memcpy(&host[s0 + s1 + s2 + s3], bmap.data(), bmap.size() * 4);
   std::memcpy(&host[s0 + s1 + s2 + s3 + s4], pmap.data(), pmap.size() * 4);
+  std::memcpy(&host[s0 + s1 + s2 + s3 + s4 + s5], wstart.data(), wstart.size() * 8);
   void* dptr = nullptr;
   hipError_t e = hipMalloc(&dptr, host.size());
   if (e != hipSuccess) return hip_fail(e, "hipMalloc(group descriptors)");
@@ -449,6 +477,8 @@ bpx_status group_build(bpx_plan* const* plans, const float* const* A, const floa
   g->d_tiles = reinterpret_cast<const GroupTile*>(base + s0 + s1 + s2);
   g->d_bmap = reinterpret_cast<const int32_t*>(base + s0 + s1 + s2 + s3);
   g->d_pmap = reinterpret_cast<const int32_t*>(base + s0 + s1 + s2 + s3 + s4);
+  g->d_wstart = reinterpret_cast<const int64_t*>(base + s0 + s1 + s2 + s3 + s4 + s5);
+  g->peel_grid = pgrid;
   g->total_b = tb;
   g->total_p = tp;
   g->max_slots = max_slots;
@@ -472,8 +502,8 @@ bpx_status group_launch(bpx_group* g, int32_t phase, hipStream_t stream) {
     }
   }
   if (phase < 0 || phase == 2) {
-    e = launch_peel_grouped(g->d_desc, g->d_pstart, g->d_pmap, g->total_p, g->max_slots,
-                            g->max_program, stream);
+    e = launch_peel_grouped(g->d_desc, g->d_pstart, g->d_pmap, g->d_wstart, g->peel_grid,
+                            g->max_slots, g->max_program, stream);
     if (e != hipSuccess) return hip_fail(e, "grouped peel launch");
   }
   return BPX_OK;

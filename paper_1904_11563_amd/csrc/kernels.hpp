@@ -155,14 +155,17 @@ hipError_t launch_split_b_grouped(const GroupDesc* d, const int64_t* bstart, con
 hipError_t launch_gemm_bf16_grouped(const GroupDesc* d, const GroupTile* tiles, int32_t n_tiles,
                                     int32_t tile, int32_t split, int32_t grid,
                                     hipStream_t stream);
-// Grouped peel: block b belongs to product pmap[b] and is block
-// b - pstart[pmap[b]] of that product's peel grid.
 // Compute units of the current device (cached per device; 256 if unknown).
 int device_cu_count();
 
+// Grouped peel: block b belongs to product pmap[b] and is block
+// b - pstart[pmap[b]] of that product's peel grid; workgroup w of the
+// persistent grid runs blocks wstart[w] .. wstart[w + 1] - 1.  The grid is
+// peel_grouped_grid(...) workgroups (as many as the CUs hold at once).
+int64_t peel_grouped_grid(int64_t total_blocks, int32_t max_slots, size_t max_program);
 hipError_t launch_peel_grouped(const GroupDesc* d, const int64_t* pstart, const int32_t* pmap,
-                               int64_t total_blocks, int32_t max_slots, size_t max_program,
-                               hipStream_t stream);
+                               const int64_t* wstart, int64_t grid, int32_t max_slots,
+                               size_t max_program, hipStream_t stream);
 
 hipError_t launch_quant_a(const Fp8Params& p, hipStream_t stream);
 hipError_t launch_quant_b(const Fp8Params& p, hipStream_t stream);

@@ -197,9 +197,11 @@ __global__ __launch_bounds__(THREADS) void peel_kernel(PeelParams p) {
 // Grouped peel: block b runs product pmap[b]'s program (vector form:
 // grouped products have N a multiple of 4).
 // Persistent over the 128-column-group items of all products (item b of
-// product i is b - pstart[i], pmap[b] = i): workgroup w takes a contiguous
-// range of items, so consecutive items mostly belong to one product and its
-// step program is staged once, not per item.  An item then costs one round
+// product i is b - pstart[i], pmap[b] = i): workgroup w takes the
+// contiguous range wstart[w] .. wstart[w + 1] - 1, split on the host so that
+// every range holds about the same number of steps (products' programs
+// differ in length), so consecutive items mostly belong to one product and
+// its step program is staged once, not per item.  An item then costs one round
 // of loads (its y values) instead of four dependent ones (item -> product ->
 // descriptor -> program -> y).  The LDS slots are per thread and rewritten
 // by each item before they are read, so items need no barrier between them;
@@ -207,12 +209,12 @@ __global__ __launch_bounds__(THREADS) void peel_kernel(PeelParams p) {
 __global__ __launch_bounds__(128) void peel_grouped_kernel(const GroupDesc* __restrict__ d,
                                                            const int64_t* __restrict__ pstart,
                                                            const int32_t* __restrict__ pmap,
-                                                           int32_t max_slots, int64_t total) {
+                                                           const int64_t* __restrict__ wstart,
+                                                           int32_t max_slots) {
   extern __shared__ v4f xs4[];  // [max_slots][128], then the current product's program
   int32_t* prog = reinterpret_cast<int32_t*>(xs4 + (size_t)max_slots * 128);
-  const int64_t per = (total + gridDim.x - 1) / gridDim.x;
-  const int64_t b0 = (int64_t)blockIdx.x * per;
-  const int64_t b1 = b0 + per < total ? b0 + per : total;
+  const int64_t b0 = wstart[blockIdx.x];
+  const int64_t b1 = wstart[blockIdx.x + 1];
   int cur = -1;
   for (int64_t b = b0; b < b1; ++b) {
     // uniform by construction; readfirstlane lets the compiler keep the
@@ -232,18 +234,22 @@ __global__ __launch_bounds__(128) void peel_grouped_kernel(const GroupDesc* __re
 
 }  // namespace
 
-hipError_t launch_peel_grouped(const GroupDesc* d, const int64_t* pstart, const int32_t* pmap,
-                               int64_t total_blocks, int32_t max_slots, size_t max_program,
-                               hipStream_t stream) {
-  if (total_blocks == 0) return hipSuccess;
+// As many workgroups as the CUs hold at once (LDS- or wave-limited), at
+// most one per item.
+int64_t peel_grouped_grid(int64_t total_blocks, int32_t max_slots, size_t max_program) {
   const size_t lds = (size_t)max_slots * 128 * 16 + max_program;
-  if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
-  // as many workgroups as the CUs hold at once (LDS- or wave-limited), at
-  // most one per item
   const int64_t per_cu = std::min<int64_t>(16, (int64_t)(160 * 1024) / (int64_t)(lds ? lds : 1));
-  const int64_t grid = std::min<int64_t>(total_blocks, (int64_t)device_cu_count() * per_cu);
+  return std::min<int64_t>(total_blocks, (int64_t)device_cu_count() * std::max<int64_t>(per_cu, 1));
+}
+
+hipError_t launch_peel_grouped(const GroupDesc* d, const int64_t* pstart, const int32_t* pmap,
+                               const int64_t* wstart, int64_t grid, int32_t max_slots,
+                               size_t max_program, hipStream_t stream) {
+  if (grid == 0) return hipSuccess;
+  const size_t lds = (size_t)max_slots * 128 * 16 + max_program;
+  if (lds > 160 * 1024 || grid > 0x7fffffff) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL(peel_grouped_kernel, dim3((unsigned)grid), dim3(128), lds, stream, d, pstart,
-                     pmap, max_slots, total_blocks);
+                     pmap, wstart, max_slots);
   return hipGetLastError();
 }
 
