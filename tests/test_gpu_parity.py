@@ -961,6 +961,42 @@ def test_grouped_graph_replay_matches_eager():
         del junk
 
 
+def test_grouped_peel_split_mixed_programs_exact():
+    """The grouped peel's workgroup ranges are cut by program cost: a group
+    mixing products with no peel steps (identity code, every block its own
+    symbol), short and long programs, and tiny and large shapes still peels
+    every block of every product exactly once (integer operands: exact), and
+    the flat GEMM's grouped tile order covers every tile."""
+    ident = bpx.Code.identity(4, 2)
+    c642 = code642()
+    c1282 = lib_code(inputs.CODE_1282)
+    cases = [(ident, [0, 1, 2, 3], 64, 96, 128), (c1282, None, 1024, 256, 768),
+             (c642, None, 32, 32, 64), (ident, [0, 1, 2, 3], 512, 64, 256),
+             (c1282, None, 256, 128, 2048), (c642, None, 1536, 96, 384)]
+    plans, As, Bs, Cs, ops = [], [], [], [], []
+    for i, (code, arrival, M, K, N) in enumerate(cases):
+        if arrival is None:
+            n = code.info()["n"]
+            arrival, _ = inputs.erasure_arrival(700 + i, n, n - code.info()["k"])
+        plans.append(bpx.Plan(code, list(arrival), 0, bpx.MODE_STRAGGLER, M, K, N,
+                              bpx.PREC_BF16X3))
+        A = inputs.integers(700 + i, inputs.TAG_A, (M, K))
+        B = inputs.integers(700 + i, inputs.TAG_B, (K, N))
+        As.append(dev(A))
+        Bs.append(dev(B))
+        Cs.append(torch.full((M, N), float("nan"), device="cuda"))
+        ops.append((A, B))
+    steps = [p.peel_program()["steps"].shape[0] for p in plans]
+    assert min(steps) == 0 and max(steps) > 4, steps
+    ws = torch.empty(bpx.group_workspace_bytes(plans), dtype=torch.uint8, device="cuda")
+    g = bpx.Group(plans, As, Bs, Cs, ws)
+    g.launch()
+    torch.cuda.synchronize()
+    for i, (A, B) in enumerate(ops):
+        R = A.astype(np.float64) @ B.astype(np.float64)
+        assert np.array_equal(host(Cs[i]).astype(np.float64), R), i
+
+
 def test_grouped_rejects_undecodable():
     code = bpx.Code.table3()
     good = bpx.Plan(code, [0, 1, 2, 3, 4], 0, bpx.MODE_STRAGGLER, 36, 8, 8, bpx.PREC_BF16X3)
