@@ -608,9 +608,17 @@ __global__ __launch_bounds__(flat::NT, 1) void coded_gemm_bf16_flat_kernel(GemmP
   __shared__ __attribute__((aligned(16))) us lds_a[flat::a_elems<SPLIT>()];
   __shared__ __attribute__((aligned(16))) us lds_b0[flat::b_elems<SPLIT>()];
   __shared__ __attribute__((aligned(16))) us lds_b1[flat::b_elems<SPLIT>()];
-  const int lin = xcd_remap(blockIdx.x, gridDim.x);
-  const int mt = lin / p.tiles_n;
-  bf16_flat_tile<SPLIT>(p, mt, lin - mt * p.tiles_n, lds_a, lds_b0, lds_b1);
+  // Each XCD takes a contiguous range of tile indices, and consecutive
+  // indices walk down groups of 8 row panels, column panel by column panel,
+  // so the tiles an XCD runs together share their A rows and B columns in
+  // its L2.
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  constexpr int kRowGroup = 8;
+  const int per_group = kRowGroup * p.tiles_n;
+  const int first = L / per_group * kRowGroup;
+  const int rows = p.tiles_m - first < kRowGroup ? p.tiles_m - first : kRowGroup;
+  const int r = L - (first / kRowGroup) * per_group;
+  bf16_flat_tile<SPLIT>(p, first + r % rows, r / rows, lds_a, lds_b0, lds_b1);
 }
 
 // Persistent grouped form of the flat tile (GroupTile.lin = mt * tiles_n + nt).
@@ -643,13 +651,19 @@ constexpr int bf16_lds_elems() {
 template <int BM, int BN, int SPLIT, int OCC>
 __global__ __launch_bounds__(kThreads, OCC) void coded_gemm_bf16_kernel(GemmParams p) {
   __shared__ __attribute__((aligned(16))) us lds[bf16_lds_elems<BM, BN, SPLIT>()];
-  const int lin = xcd_remap(blockIdx.x, gridDim.x);
-  const int per_sym = p.tiles_m * p.tiles_n;
-  const int si = lin / per_sym;
-  const int rem = lin - si * per_sym;
-  const int mt = rem / p.tiles_n;
-  const int nt = rem - mt * p.tiles_n;
-  bf16_tile<BM, BN, SPLIT>(p, si, mt, nt, lds);
+  // Row panels of all symbols in one sequence (every symbol multiplies the
+  // same B), walked in groups of 8, column panel by column panel, as in the
+  // flat kernel.
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  constexpr int kRowGroup = 8;
+  const int panels = p.n_sym * p.tiles_m;
+  const int per_group = kRowGroup * p.tiles_n;
+  const int first = L / per_group * kRowGroup;
+  const int rows = panels - first < kRowGroup ? panels - first : kRowGroup;
+  const int r = L - (first / kRowGroup) * per_group;
+  const int rp = first + r % rows;
+  const int si = rp / p.tiles_m;
+  bf16_tile<BM, BN, SPLIT>(p, si, rp - si * p.tiles_m, r / rows, lds);
 }
 
 // Grouped split-B: a flat range of 64 x 64 transpose blocks over products
