@@ -344,7 +344,9 @@ bpx_status bpx_coded_matmul_grouped(bpx_plan* const* plans, const float* const* 
 int32_t bpx_tile_count(int32_t prec);
 /* Order in which the FP32 GEMM walks its output tiles: row panels (symbol x
  * m-tile) in groups of group_m, each group finished column panel by column
- * panel (1 = plain row-major order).  Affects speed and L2 reuse only. */
+ * panel (1 = plain row-major order).  Affects speed and L2 reuse only.  The
+ * BF16 / BF16x3 kernels (and the grouped launch's tile lists) walk fixed
+ * groups of 8 row panels, the FP8 kernel groups of 4. */
 bpx_status bpx_set_tile_order(int32_t group_m);
 bpx_status bpx_set_tile_table(const int32_t* table, int32_t n_entries);
 bpx_status bpx_force_tile(int32_t tile);
