@@ -360,21 +360,21 @@ bpx_status group_build(bpx_plan* const* plans, const float* const* A, const floa
       nt = (int64_t)p.n_sym * p.tiles_m * p.tiles_n;
     }
     d.tile = t;
-    // Flat tiles are listed in groups of kRowGroup row panels, column panel
-    // by column panel, so the run of consecutive tiles one XCD takes covers
-    // a few column panels of B for several row panels and shares both in
-    // that XCD's L2 (row by row, a run spans every column panel of B and
-    // uses each only about twice).
+    // Tiles are listed in groups of kRowGroup row panels, column panel by
+    // column panel, so the run of consecutive tiles one XCD takes covers a
+    // few column panels of B for several row panels and shares both in that
+    // XCD's L2 (row by row, a run spans every column panel of B and uses
+    // each only about twice).  Row panel rp is a stacked-row panel (flat
+    // tiles) or symbol rp / tiles_m's m-tile (per-symbol tiles, which all
+    // multiply the same B); either way the tile index is rp tiles_n + column.
     constexpr int64_t kRowGroup = 8;
+    const int64_t panels = p.tiles_n > 0 ? nt / p.tiles_n : 0;
     for (int64_t q = 0; q < nt; ++q) {
-      int64_t l = q;
-      if (bf16_tile_is_flat(t)) {
-        const int64_t per_group = kRowGroup * p.tiles_n;
-        const int64_t first = q / per_group * kRowGroup;
-        const int64_t rows = std::min<int64_t>(kRowGroup, p.tiles_m - first);
-        const int64_t r = q % per_group;
-        l = (first + r % rows) * p.tiles_n + r / rows;
-      }
+      const int64_t per_group = kRowGroup * p.tiles_n;
+      const int64_t first = q / per_group * kRowGroup;
+      const int64_t rows = std::min<int64_t>(kRowGroup, panels - first);
+      const int64_t r = q % per_group;
+      const int64_t l = (first + r % rows) * p.tiles_n + r / rows;
       by_tile[t].push_back(GroupTile{i, (int32_t)l});
       key[t].push_back(pl->K);
     }
