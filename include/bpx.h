@@ -50,7 +50,7 @@ typedef enum {
   BPX_E_UNDECODABLE = -2,  /* the available columns do not peel               */
   BPX_E_NOMEM = -3,        /* host or device allocation failed                */
   BPX_E_HIP = -4,          /* a HIP runtime call failed                       */
-  BPX_E_UNSUPPORTED = -5   /* valid request outside what this build handles   */
+  BPX_E_UNSUPPORTED = -5   /* valid request outside what this library handles */
 } bpx_status;
 
 typedef enum {

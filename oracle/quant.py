@@ -2,8 +2,8 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-The paper's symbols are exact XOR sums; the FP8 path is this build's
-precision choice, so this module follows the OCP 8-bit floating point
+The paper's symbols are exact XOR sums; the FP8 path is this
+implementation's precision choice, so this module follows the OCP 8-bit floating point
 definition of E4M3 (1 sign bit, 4 exponent bits with bias 7, 3 mantissa
 bits, no infinities, the all-ones pattern is NaN): normal values
 2^(e-7) (1 + m/8) for exponent field e in 1..15 (largest 448), subnormal
