@@ -246,6 +246,50 @@ def overhead_closed_a(n: int, k: int, b: int) -> float:
     return (k - 1) / (2 * k * b) * (phi(n) + phi(n - 1) - phi(n - k) - phi(max(n - k - 1, 0)))
 
 
+def overhead_direct_total(code: Code, need: int) -> float:
+    """Worst-case overhead in symbols: the largest number of bins (empty ones
+    included) that any ``need`` columns hold, divided by the k*b data symbols,
+    minus one.  This is the normalisation of the exact overhead expression of
+    Appendix B, where ``need`` = ceil(k / 2^qe) projections suffice; for
+    Construction A (need = k) it equals ``overhead_direct``."""
+    sizes = code.col_sizes()
+    best = max(sum(sizes[i] for i in c) for c in combinations(range(code.n), need))
+    return best / code.kb - 1.0
+
+
+def construction_b_needed(k: int, qe: int) -> int:
+    """Projections that suffice for Construction B by the Katz criterion
+    (Appendix B): t 2^qe >= k, i.e. t = ceil(k / 2^qe)."""
+    return -(-k // (1 << qe))
+
+
+def overhead_closed_b(n: int, k: int, b: int, qe: int) -> float:
+    """Exact worst-case overhead of Construction B (Appendix B).
+
+    The t = ceil(k/2^qe) columns with the largest |p| hold
+    sum (|p_i| (k-1) + 2^qe (b-1) + 1) bins.  Construction B's n odd p values
+    contain those of n - t projections as the n - t smallest |p|, so by Lemma
+    B.1 the largest t of them sum to L(n) - L(n-t), L being Lemma B.1's sum.
+    Hence eps = (2^qe (b-1) t + (k-1) (L(n) - L(n-t)) + t) / (kb) - 1.
+    (The printed exact expression of Appendix B writes the |p| sum with the
+    phi of Appendix A, which is Construction A's sum, not B's; this function
+    takes B's own p set.)
+    """
+    t = construction_b_needed(k, qe)
+    return ((1 << qe) * (b - 1) * t + (k - 1) * (lemma_b1(n) - lemma_b1(n - t)) + t) \
+        / (k * b) - 1.0
+
+
+def overhead_bracket_b(n: int, k: int, b: int, qe: int):
+    """Lower and upper bound on Construction B's overhead from the |p|-sum
+    bracket of Appendix B, (t2^2 - t1^2 -+ 1)/2 with t2 = n, t1 = n - t."""
+    t = construction_b_needed(k, qe)
+    base = (1 << qe) * (b - 1) * t + t
+    span = n * n - (n - t) ** 2
+    return ((base + (k - 1) * (span - 1) / 2) / (k * b) - 1.0,
+            (base + (k - 1) * (span + 1) / 2) / (k * b) - 1.0)
+
+
 def overhead_approx_a(n: int, k: int, b: int) -> float:
     """Large-b approximation of Appendix A: (k-1)(2n-k)/(4b)."""
     return (k - 1) * (2 * n - k) / (4 * b)

@@ -38,3 +38,30 @@ def load_golden_table(name):
                 col.append(tuple(ids))
             cols.append(col)
     return cols
+
+
+def load_release_tables():
+    """Parse tests/golden/release_tables.txt: a list of dicts with the case
+    name, code name, mode name, arrival, n_lost, prefix_m and per-id
+    (releaser, depth)."""
+    path = os.path.join(ROOT, "tests", "golden", "release_tables.txt")
+    cases = []
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            parts = line.split()
+            if parts[0] == "case":
+                cases.append({"name": parts[1], "code": parts[2], "mode": parts[3],
+                              "arrival": [int(x) for x in parts[4].split(",")],
+                              "n_lost": int(parts[5]), "prefix_m": int(parts[6]),
+                              "release": {}})
+            else:
+                s, g, d = (int(x) for x in parts)
+                cases[-1]["release"][s] = (g, d)
+    return cases
+
+
+# The hand-made four-column code of release_tables.txt (k = 3, b = 1).
+K3B1_COLUMNS = [[(0,)], [(1,)], [(0, 1, 2)], [(1, 2)]]

@@ -312,3 +312,24 @@ def test_two_dimensional_plans():
         bpx.Plan(bpx.Code.identity(4, 2), [0, 1, 2, 3], 0, bpx.MODE_STRAGGLER, 8, 8, 16,
                  two_d=True)
     assert e.value.status == bpx.E_INVALID
+
+
+def test_plan_matches_hand_worked_release_tables():
+    # The library's schedule on the hand-worked cases of
+    # tests/golden/release_tables.txt (canonical (degree, g) release rule).
+    from conftest import K3B1_COLUMNS, load_release_tables
+    modes = {"erasure": bpx.MODE_ERASURE, "straggler": bpx.MODE_STRAGGLER,
+             "full": bpx.MODE_FULL, "min": bpx.MODE_MIN}
+    for c in load_release_tables():
+        if c["code"] == "table1":
+            code = bpx.Code.table1()
+        elif c["code"] == "table3":
+            code = bpx.Code.table3()
+        else:
+            code = bpx.Code.from_columns(4, 3, 1, K3B1_COLUMNS)
+        plan = bpx.Plan(code, c["arrival"], c["n_lost"], modes[c["mode"]], 64, 8, 8)
+        inf = plan.info()
+        sch = plan.schedule()
+        assert inf["decodable"] and inf["prefix_m"] == c["prefix_m"], c["name"]
+        for s, (g, d) in c["release"].items():
+            assert (int(sch["releaser"][s]), int(sch["depth"][s])) == (g, d), (c["name"], s)

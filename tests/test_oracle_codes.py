@@ -169,6 +169,79 @@ def test_katz_implies_peeling(qe):
                         assert _peels(_col_syms(c, sub), c.kb), (k, b, qe, sub)
 
 
+def test_katz_criterion_is_exact_on_small_grids():
+    # Katz's theorem is an equivalence: when sum|p| < b and sum|q| < k a
+    # non-zero "ghost" (the product of the projections' two-point kernels)
+    # fits in the grid and has every projection zero, so the system is
+    # singular and BP cannot finish; otherwise BP peels the grid.  Checked in
+    # both directions over every set of up to three distinct coprime
+    # directions on every grid up to 5 x 5, which also pins the orientation
+    # of the criterion against the grid of Eq. (moj1) (the swapped pairing,
+    # sum|p| >= k or sum|q| >= b, disagrees with BP on many of these sets).
+    from math import gcd
+    dirs = [(p, q) for p in range(-3, 4) for q in range(0, 3)
+            if gcd(p, q) == 1 and not (q == 0 and p <= 0)]
+    swapped_disagrees = 0
+    for k in range(1, 6):
+        for b in range(1, 6):
+            cols = {d: codes.mojette_column(d[0], d[1], k, b) for d in dirs}
+            for t in (1, 2, 3):
+                for sub in combinations(dirs, t):
+                    syms, g = [], 0
+                    for d in sub:
+                        for sym in cols[d]:
+                            syms.append((g, sym))
+                            g += 1
+                    ok = _peels(syms, k * b)
+                    assert ok == codes.katz(list(sub), k, b), (k, b, sub)
+                    swapped = (sum(abs(p) for p, _ in sub) >= k or
+                               sum(abs(q) for _, q in sub) >= b)
+                    swapped_disagrees += ok != swapped
+    assert swapped_disagrees > 0
+    # hand-checked instances: the example of Sec. III-C (k = 3, b = 4,
+    # directions (-1,1), (0,1), (1,1): sum|q| = 3 = k) and a single direction
+    assert codes.katz([(-1, 1), (0, 1), (1, 1)], 3, 4)
+    assert not codes.katz([(1, 1)], 3, 4)
+    assert codes.katz([(4, 1)], 3, 4)
+
+
+def test_construction_b_overhead_exact():
+    # Appendix B: t = ceil(k/2^qe) projections suffice; the worst-case
+    # overhead counts the bins of the t columns with the largest |p| over
+    # the k*b data symbols.  Closed form (Lemma B.1 on B's odd p set)
+    # against the direct maximum over every t-column choice of the built
+    # code, and inside the bracket from the |p|-sum bounds of Appendix B.
+    for qe in (1, 2, 3):
+        for n in range(2, 12):
+            for k in range(1, 12):
+                t = codes.construction_b_needed(k, qe)
+                if t > n:
+                    continue
+                for b in (1, 2, 3, 5, 8):
+                    c = codes.mojette(k, b, n, qe)
+                    direct = codes.overhead_direct_total(c, t)
+                    assert abs(direct - codes.overhead_closed_b(n, k, b, qe)) < 1e-12, \
+                        (qe, n, k, b)
+                    lo, hi = codes.overhead_bracket_b(n, k, b, qe)
+                    assert lo - 1e-12 <= direct <= hi + 1e-12
+    # the FP32 Construction B workload: k = 8, b = 4, n = 12, qe = 1 needs
+    # t = 4 columns; the four with |p| = 11, 11, 9, 9 hold 4*(2*3+1) + 7*40
+    # = 308 bins for 32 data symbols
+    assert codes.overhead_closed_b(12, 8, 4, 1) == 308 / 32 - 1
+
+
+def test_construction_b_decodes_from_needed_columns():
+    # Katz with sum|q| = t 2^qe >= k: any t = ceil(k/2^qe) columns decode.
+    for qe in (1, 2):
+        for k in range(2, 7):
+            for b in range(2, 6):
+                t = codes.construction_b_needed(k, qe)
+                n = t + 3
+                c = codes.mojette(k, b, n, qe)
+                for sub in combinations(range(n), t):
+                    assert _peels(_col_syms(c, sub), c.kb), (qe, k, b, sub)
+
+
 def test_construction_a_any_k_projections_decode():
     # Construction A: any k projections have sum|q| = k, so they decode.
     for k in range(2, 6):

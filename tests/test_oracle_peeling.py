@@ -188,3 +188,43 @@ def test_min_mode_computes_releasers_only():
     plan = make_plan(c, [4, 3, 0, 1, 2], 0, MIN)
     assert plan.decodable
     assert plan.computed == sorted(set(plan.releaser))
+
+
+# ------------------------------------------------- hand-worked schedules --
+
+def _golden_code(name):
+    from conftest import K3B1_COLUMNS
+    if name == "table1":
+        return codes.table1()
+    if name == "table3":
+        return codes.table3()
+    assert name == "k3b1"
+    return codes.Code("array", n=4, k=3, b=1, columns=K3B1_COLUMNS)
+
+
+_MODES = {"erasure": ERASURE, "straggler": STRAGGLER, "full": FULL, "min": MIN}
+
+
+@pytest.mark.parametrize("case", [c["name"] for c in __import__("conftest").load_release_tables()])
+def test_release_schedule_matches_hand_worked_table(case):
+    # tests/golden/release_tables.txt: releaser and depth of every id worked
+    # out by hand with the canonical (degree, g) release rule (Sec. I-A's BP
+    # leaves the choice open); two of the cases have several candidates for
+    # one id in the same round, one of them of different degrees.
+    from conftest import load_release_tables
+    c = [x for x in load_release_tables() if x["name"] == case][0]
+    code = _golden_code(c["code"])
+    plan = make_plan(code, c["arrival"], c["n_lost"], _MODES[c["mode"]])
+    assert plan.decodable and plan.prefix_m == c["prefix_m"]
+    for s, (g, d) in c["release"].items():
+        assert (plan.releaser[s], plan.depth[s]) == (g, d), (case, s)
+    assert len(c["release"]) == code.kb
+
+
+def test_release_rule_prefers_low_degree_then_low_g():
+    # the same rule on bare symbol lists: an id with candidates of degrees 3
+    # and 2 takes the degree-2 one; equal degrees take the smaller g
+    rel, dep = peel([(0, (0,)), (1, (1,)), (2, (0, 1, 2)), (3, (1, 2))], 3)
+    assert rel == {0: 0, 1: 1, 2: 3} and dep == {0: 1, 1: 1, 2: 2}
+    rel, _ = peel([(5, (0,)), (7, (0, 1)), (9, (0, 1))], 2)
+    assert rel == {0: 5, 1: 7}

@@ -51,3 +51,33 @@ def test_block_scaling():
     assert err2 < err / 8
     s0, c0 = quant.quantize_block(np.zeros((4, 4)))
     assert s0 == 1.0 and not c0.any()
+
+
+def test_coded_block_fp32_is_the_block_sum_on_integers():
+    # On integer operands every float32 addition is exact, so the float32
+    # coded block must equal the float64 encode (the plain sum of the member
+    # blocks, Sec. III-A's XOR read as a real sum), including the zero rows
+    # of a ragged last block (M = 7 Mb + 11 here) and members in any order.
+    from oracle import codes as ocodes
+    from oracle import pipeline
+    rng = np.random.default_rng(3)
+    kb, Mb, K = 8, 16, 40
+    M = (kb - 1) * Mb + 11   # Mb = ceil(M / kb) = 16, the last block ragged
+    A = rng.integers(-8, 9, size=(M, K)).astype(np.float32)
+    cols = [[(0, 3), (7,)], [(1, 6, 7), (2, 4, 5, 6)], [(5,), (0, 1, 2, 3, 4, 5, 6, 7)],
+            [(6, 7), (3,)]]
+    code = ocodes.Code("array", n=4, k=4, b=2, columns=cols)
+    ref = pipeline.encode(A, code, range(8))
+    for g, _, members in code.symbols():
+        got = quant.coded_block_fp32(A, Mb, list(reversed(members)), M)
+        assert got.dtype == np.float32 and got.shape == (Mb, K)
+        assert np.array_equal(got.astype(np.float64), ref[g]), g
+
+
+def test_coded_block_fp32_adds_members_in_ascending_order():
+    # Order pin, worked by hand: blocks 0, 1, 2 hold 2^24, 1 and -2^24.
+    # Ascending order: 2^24 + 1 rounds (ties to even) to 2^24, minus 2^24
+    # gives 0.  Descending order would give -2^24 + 1 (exact) + 2^24 = 1.
+    A = np.array([[2.0 ** 24], [1.0], [-(2.0 ** 24)]], dtype=np.float32)
+    got = quant.coded_block_fp32(A, 1, [2, 0, 1], 3)
+    assert got.tolist() == [[0.0]]
