@@ -21,9 +21,15 @@
  *  - Return value is a bpx_status; on failure bpx_last_error() returns a
  *    message (thread-local, valid until the next call on the same thread).
  *  - Handles (bpx_code, bpx_plan) are created and freed by the library and
- *    are immutable after creation; distinct handles may be used from
- *    distinct threads.  Arrays returned through "borrowed" pointers live as
- *    long as the handle.
+ *    their contents (code, schedule) do not change after creation; distinct
+ *    handles may be used from distinct threads, and one plan may be shared
+ *    by threads (its device tables are uploaded once, under a lock, by the
+ *    first device call).  Arrays returned through "borrowed" pointers live
+ *    as long as the handle.
+ *  - The tuning setters (bpx_set_tile_table, bpx_force_tile,
+ *    bpx_set_tile_order) change process-wide state read by every later
+ *    device call; call them before device calls start, not concurrently
+ *    with them.
  *  - Host functions (code and plan construction, queries) never touch the GPU.
  *  - Device functions take caller-owned device pointers, enqueue on the given
  *    HIP stream and return without synchronising.  They allocate nothing

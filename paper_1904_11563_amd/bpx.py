@@ -20,7 +20,9 @@ import numpy as np
 import torch  # noqa: F401,E402
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libbpx.so")
+# BPX_LIBRARY selects another build of the same library (the host-sanitizer
+# build that the CPU tests run); the default is the in-tree libbpx.so.
+LIB_PATH = os.environ.get("BPX_LIBRARY") or os.path.join(_HERE, "libbpx.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
@@ -314,11 +316,27 @@ class Plan:
 
 # ----------------------------------------------------------------- device --
 
-def _mat(t, name):
+def _mat(t, name, shape=None):
+    """Pointer and leading dimension of a row-major float32 device matrix;
+    shape, when given, is the (rows, cols) the plan expects."""
     import torch
-    if t.dtype != torch.float32 or not t.is_cuda or t.dim() != 2 or t.stride(1) != 1:
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda or \
+            t.dim() != 2 or t.stride(1) != 1:
         raise ValueError(f"{name} must be a 2-D float32 device tensor with unit column stride")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, the plan expects {tuple(shape)}")
     return _p(t.data_ptr()), t.stride(0)
+
+
+def _dense(t, name, shape):
+    """Pointer of a dense (contiguous) row-major float32 device matrix of the
+    given shape: grouped products bake lda = K, ldb = ldc = N."""
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda or \
+            not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must be a contiguous float32 device tensor of shape "
+                         f"{tuple(shape)}")
+    return _p(t.data_ptr())
 
 
 def _stream(stream):
@@ -328,8 +346,11 @@ def _stream(stream):
 
 
 def _ws(ws):
+    import torch
     if ws is None:
         return _p(0), 0
+    if not isinstance(ws, torch.Tensor) or not ws.is_cuda or not ws.is_contiguous():
+        raise ValueError("workspace must be a contiguous device tensor")
     return _p(ws.data_ptr()), ws.numel() * ws.element_size()
 
 
@@ -340,38 +361,51 @@ def alloc_workspace(plan: Plan, device="cuda"):
 
 
 def encode(plan: Plan, A, out, stream=None):
-    a, lda = _mat(A, "A")
+    import torch
+    a, lda = _mat(A, "A", (plan.M, plan.K))
+    _, need = plan.workspace_bytes()
+    if not isinstance(out, torch.Tensor) or out.dtype != torch.float32 or not out.is_cuda or \
+            not out.is_contiguous() or out.numel() * 4 < need:
+        raise ValueError(f"out must be a contiguous float32 device tensor of at least "
+                         f"{need} bytes")
     _check(_lib.bpx_encode(plan._h, a, lda, _p(out.data_ptr()), _stream(stream)))
 
 
 def coded_gemm(plan: Plan, A, B, C_out, ws, stream=None):
-    a, lda = _mat(A, "A")
-    b, ldb = _mat(B, "B")
-    c, ldc = _mat(C_out, "C")
+    a, lda = _mat(A, "A", (plan.M, plan.K))
+    b, ldb = _mat(B, "B", (plan.K, plan.N))
+    c, ldc = _mat(C_out, "C", (plan.M, plan.N))
     w, wb = _ws(ws)
     _check(_lib.bpx_coded_gemm(plan._h, a, lda, b, ldb, c, ldc, w, wb, _stream(stream)))
 
 
 def peel_decode(plan: Plan, ws, C_out, stream=None):
-    c, ldc = _mat(C_out, "C")
+    c, ldc = _mat(C_out, "C", (plan.M, plan.N))
     w, wb = _ws(ws)
     _check(_lib.bpx_peel_decode(plan._h, w, wb, c, ldc, _stream(stream)))
 
 
 def coded_matmul(plan: Plan, A, B, C_out, ws, stream=None):
-    a, lda = _mat(A, "A")
-    b, ldb = _mat(B, "B")
-    c, ldc = _mat(C_out, "C")
+    a, lda = _mat(A, "A", (plan.M, plan.K))
+    b, ldb = _mat(B, "B", (plan.K, plan.N))
+    c, ldc = _mat(C_out, "C", (plan.M, plan.N))
     w, wb = _ws(ws)
     _check(_lib.bpx_coded_matmul(plan._h, a, lda, b, ldb, c, ldc, w, wb, _stream(stream)))
 
 
-def coded_matmul_grouped(plans, As, Bs, Cs, ws, stream=None):
+def _group_operands(plans, As, Bs, Cs):
     n = len(plans)
+    if not (len(As) == len(Bs) == len(Cs) == n) or n < 1:
+        raise ValueError("plans, A, B and C must be non-empty lists of one length")
     P = (_p * n)(*[p._h for p in plans])
-    A = (_p * n)(*[_p(a.data_ptr()) for a in As])
-    B = (_p * n)(*[_p(b.data_ptr()) for b in Bs])
-    Cc = (_p * n)(*[_p(c.data_ptr()) for c in Cs])
+    A = (_p * n)(*[_dense(a, f"A[{i}]", (p.M, p.K)) for i, (p, a) in enumerate(zip(plans, As))])
+    B = (_p * n)(*[_dense(b, f"B[{i}]", (p.K, p.N)) for i, (p, b) in enumerate(zip(plans, Bs))])
+    Cc = (_p * n)(*[_dense(c, f"C[{i}]", (p.M, p.N)) for i, (p, c) in enumerate(zip(plans, Cs))])
+    return n, P, A, B, Cc
+
+
+def coded_matmul_grouped(plans, As, Bs, Cs, ws, stream=None):
+    n, P, A, B, Cc = _group_operands(plans, As, Bs, Cs)
     w, wb = _ws(ws)
     _check(_lib.bpx_coded_matmul_grouped(P, A, B, Cc, n, w, wb, _stream(stream)))
 
@@ -389,11 +423,7 @@ class Group:
     are fixed at creation, so launch() can be captured in a HIP graph."""
 
     def __init__(self, plans, As, Bs, Cs, ws):
-        n = len(plans)
-        P = (_p * n)(*[p._h for p in plans])
-        A = (_p * n)(*[_p(a.data_ptr()) for a in As])
-        B = (_p * n)(*[_p(b.data_ptr()) for b in Bs])
-        Cc = (_p * n)(*[_p(c.data_ptr()) for c in Cs])
+        n, P, A, B, Cc = _group_operands(plans, As, Bs, Cs)
         w, wb = _ws(ws)
         h = _p()
         _check(_lib.bpx_group_create(P, A, B, Cc, n, w, wb, C.byref(h)))

@@ -30,6 +30,29 @@ EXTRA = {"gemm_f32.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
          "gemm2d.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"]}
 
 
+# Host-sanitizer build (CPU tests only): the integer host core (code
+# construction, planning, the C ABI) built with AddressSanitizer and
+# UndefinedBehaviorSanitizer on its host pass; device code is unchanged.
+HOST_CORE = ("code.cpp", "plan.cpp", "abi.cpp")
+SAN_FLAGS = "-Xarch_host -fsanitize=address -Xarch_host -fsanitize=undefined".split()
+SAN_LIB = os.path.join(BUILD, "san", "libbpx_san.so")
+
+
+def sanitizer_runtime():
+    """Path of the compiler's shared AddressSanitizer runtime (to preload)."""
+    r = subprocess.run([HIPCC, "-print-file-name=libclang_rt.asan-x86_64.so"],
+                       capture_output=True, text=True)
+    path = r.stdout.strip()
+    if not os.path.isabs(path):
+        base = os.path.join(os.path.dirname(os.path.realpath(HIPCC)), "..", "llvm", "lib",
+                            "clang")
+        for v in sorted(os.listdir(base)) if os.path.isdir(base) else []:
+            cand = os.path.join(base, v, "lib", "linux", "libclang_rt.asan-x86_64.so")
+            if os.path.exists(cand):
+                path = cand
+    return path
+
+
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
                   if f.endswith((".hip", ".cpp")))
@@ -67,5 +90,38 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_sanitized() -> str:
+    """libbpx_san.so: the host core with ASan + UBSan, linked with the
+    regular device objects (built first if missing)."""
+    if not all(os.path.exists(os.path.join(BUILD, os.path.basename(f) + ".o"))
+               for f in sources()):
+        build()
+    out_dir = os.path.dirname(SAN_LIB)
+    os.makedirs(out_dir, exist_ok=True)
+    objs = []
+    for src in sources():
+        name = os.path.basename(src)
+        if name in HOST_CORE:
+            obj = os.path.join(out_dir, name + ".o")
+            cmd = [HIPCC, "-O1", "-g", "-fPIC", "-std=c++17", "--offload-arch=gfx950",
+                   "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"] + SAN_FLAGS + \
+                  ["-x", "hip", "-c", src, "-o", obj]
+            r = subprocess.run(cmd, capture_output=True, text=True)
+            if r.returncode != 0:
+                raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stderr}")
+            objs.append(obj)
+        else:
+            objs.append(os.path.join(BUILD, name + ".o"))
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950"] + SAN_FLAGS + \
+        ["-shared-libasan", "-o", SAN_LIB] + objs
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stderr}")
+    return SAN_LIB
+
+
 if __name__ == "__main__":
-    print(build(verbose=True))
+    if "--sanitize" in sys.argv:
+        print(build_sanitized())
+    else:
+        print(build(verbose=True))

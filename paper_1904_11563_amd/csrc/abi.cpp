@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -72,10 +73,16 @@ int32_t choose_tile(int32_t prec, int64_t Mb, int64_t N, int64_t K) {
   return 6;
 }
 
+// Plans upload their tables lazily on the first device call; the lock makes
+// that first call safe when threads share a plan (the tables are written
+// once and never change afterwards).
+std::mutex g_upload_mutex;
+
 bpx_status upload(bpx_plan* plan) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lock(g_upload_mutex);
   if (plan->dev_block) {
     if (plan->dev_id != dev)
       return fail(BPX_E_INVALID, "plan tables live on another device");
@@ -558,6 +565,7 @@ bpx_status bpx_code_from_csr(int32_t n, int32_t k, int32_t b, const int32_t* col
     if (col_ptr[j + 1] < col_ptr[j]) return fail(BPX_E_INVALID, "col_ptr not ascending");
   const int32_t ns = col_ptr[n];
   if (sym_ptr[0] != 0) return fail(BPX_E_INVALID, "sym_ptr[0] must be 0");
+  if (ns > 0 && sym_ptr[ns] > 0 && !sym_data) return fail(BPX_E_INVALID, "null sym_data");
   for (int32_t g = 0; g < ns; ++g) {
     if (sym_ptr[g + 1] < sym_ptr[g]) return fail(BPX_E_INVALID, "sym_ptr not ascending");
     for (int32_t e = sym_ptr[g]; e < sym_ptr[g + 1]; ++e) {
