@@ -202,6 +202,7 @@ def run_single(args):
     C = Cd.cpu().numpy()
     R = A[rows].astype(np.float64) @ B.astype(np.float64)
     rel_err = float(np.linalg.norm(C[rows] - R) / np.linalg.norm(R))
+    worst = worst_errors(C[rows], R, rows, Mb)
 
     refs = {}
     if not args.no_ref:
@@ -282,6 +283,11 @@ def run_single(args):
            "depth_max": info["depth_max"], "parallelism": "none (1 GPU)"}
     out = header(args, value, ms, prec_name, cfg)
     out.update({"rel_err": rel_err, "rel_err_sample": f"{len(rows)} rows x all columns",
+                "rel_err_worst": worst,
+                # the plan (arrival prefix + schedule, host) is made once per
+                # arrival pattern, outside the timed region; with it per step:
+                "ms_per_step_incl_plan": ms + plan_us * 1e-3,
+                "value_incl_plan": useful / ((ms + plan_us * 1e-3) * 1e-3) / 1e12,
                 "times_ms": {"coded_gemm_call": gemm_ms, "peel": peel_ms,
                              "plan_host_us": plan_us, "code_build_s": code_s},
                 "roofline": roofline, "hbm": hbm})
@@ -294,6 +300,25 @@ def run_single(args):
         out["cpu_baseline"] = cpu_single(A, B, code, arrival, lost, mode, w, args.cpu_seconds,
                                          two_d)
     return out
+
+
+def worst_errors(C, R, rows, Mb):
+    """Worst relative error over the sampled rows and over the data blocks'
+    sampled rows (the Frobenius error of the whole sample hides rows whose
+    error grew along a release chain or through cancellation)."""
+    import numpy as np
+    num = np.sum((C.astype(np.float64) - R) ** 2, axis=1)
+    den = np.maximum(np.sum(R ** 2, axis=1), 1e-300)
+    per_row = np.sqrt(num / den)
+    blocks = np.asarray(rows) // Mb
+    best_b, best_e = -1, -1.0
+    for b in np.unique(blocks):
+        m = blocks == b
+        e = float(np.sqrt(num[m].sum() / den[m].sum()))
+        if e > best_e:
+            best_b, best_e = int(b), e
+    return {"row": float(per_row.max()), "row_at": int(rows[int(per_row.argmax())]),
+            "block": best_e, "block_at": best_b}
 
 
 def latency_model(bpx, code, w, prec, gemm_ms, n_comp, hbm, refs, spec, samples=500):
@@ -485,13 +510,20 @@ def run_batch(args):
 
     # error: 8 sampled rows of every product against float64
     num = den = 0.0
+    worst = {"product": 0.0, "product_at": -1, "row": 0.0, "row_at": [-1, -1]}
     for i, (M, K, N, k) in enumerate(shapes):
         rows = np.linspace(0, M - 1, 8).astype(int)
         A = As[i][rows].double().cpu().numpy()
         R = A @ Bs[i].double().cpu().numpy()
         Cr = Cs[i][rows].double().cpu().numpy()
-        num += float(np.sum((Cr - R) ** 2))
-        den += float(np.sum(R ** 2))
+        pn, pd = float(np.sum((Cr - R) ** 2)), float(np.sum(R ** 2))
+        num += pn
+        den += pd
+        if np.sqrt(pn / pd) > worst["product"]:
+            worst["product"], worst["product_at"] = float(np.sqrt(pn / pd)), i
+        rw = np.sqrt(np.sum((Cr - R) ** 2, axis=1) / np.sum(R ** 2, axis=1))
+        if rw.max() > worst["row"]:
+            worst["row"], worst["row_at"] = float(rw.max()), [i, int(rows[int(rw.argmax())])]
     rel_err = float(np.sqrt(num / den))
 
     cfg = {"workload": "batch", "products": len(shapes),
@@ -504,6 +536,7 @@ def run_batch(args):
            "parallelism": "none (1 GPU)"}
     out = header(args, value, ms, prec_name, cfg)
     out.update({"rel_err": rel_err, "rel_err_sample": "8 rows x all columns of every product",
+                "rel_err_worst": worst,
                 "times_ms": {"split_b": phase_ms[0], "grouped_gemm": phase_ms[1],
                              "peel": phase_ms[2]},
                 "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[prec_name],
