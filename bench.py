@@ -106,6 +106,36 @@ def timed(torch, fn, steps, stream=None):
     return e0.elapsed_time(e1) / steps
 
 
+def capture(torch, fn):
+    """A HIP graph holding the launches of fn (captured on a side stream)."""
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        fn()                     # warm, not captured
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=s):
+            fn()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    return graph
+
+
+def graph_ms(torch, fn, steps, warmup=3):
+    """Mean wall milliseconds per replay of fn captured in a HIP graph,
+    bracketed by device synchronisation."""
+    g = capture(torch, fn)
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
 def build_code(bpx, spec):
     if spec.kind == "search":
         return bpx.Code.search(spec.n, spec.k, spec.b, spec.sigma, spec.seed, spec.restarts,
@@ -169,25 +199,39 @@ def run_single(args):
     ws = bpx.alloc_workspace(plan, dev)
     stream = torch.cuda.current_stream()
 
+    fused = plan.fused()
     for _ in range(args.warmup):
         bpx.coded_matmul(plan, Ad, Bd, Cd, ws)
     torch.cuda.synchronize()
 
-    # timed region: K whole steps; events split each step into its launches
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    # timed region: K whole steps, each one replay of a HIP graph holding the
+    # step's launches (coded GEMM + peel, or the one fused launch)
+    step_graph = capture(torch, lambda: bpx.coded_matmul(plan, Ad, Bd, Cd, ws))
+    for _ in range(args.warmup):
+        step_graph.replay()
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    for e0, e1, e2 in ev:
-        e0.record(stream)
-        bpx.coded_gemm(plan, Ad, Bd, Cd, ws)
-        e1.record(stream)
-        bpx.peel_decode(plan, ws, Cd)
-        e2.record(stream)
+    for _ in range(args.steps):
+        step_graph.replay()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
-    gemm_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in ev]))
-    peel_ms = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
     ms = wall * 1e3 / args.steps
+
+    # per-launch durations: events on the launch stream around each launch
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    for e0, e1, e2 in ev:
+        e0.record(stream)
+        if fused:
+            bpx.coded_matmul(plan, Ad, Bd, Cd, ws)
+        else:
+            bpx.coded_gemm(plan, Ad, Bd, Cd, ws)
+        e1.record(stream)
+        if not fused:
+            bpx.peel_decode(plan, ws, Cd)
+        e2.record(stream)
+    torch.cuda.synchronize()
+    gemm_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in ev]))
+    peel_ms = float(np.mean([b.elapsed_time(c) for _, b, c in ev])) if not fused else 0.0
 
     useful = 2.0 * w.M * w.N * w.K
     value = useful / (ms * 1e-3) / 1e12
@@ -215,12 +259,8 @@ def run_single(args):
         Cu = torch.empty_like(Cd)
         for _ in range(3):
             bpx.coded_matmul(uplan, Ad, Bd, Cu, uws)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(args.steps):
-            bpx.coded_matmul(uplan, Ad, Bd, Cu, uws)
-        torch.cuda.synchronize()
-        refs["uncoded_own_tflops"] = useful / ((time.perf_counter() - t1) / args.steps) / 1e12
+        refs["uncoded_own_tflops"] = useful / (graph_ms(
+            torch, lambda: bpx.coded_matmul(uplan, Ad, Bd, Cu, uws), args.steps) * 1e-3) / 1e12
         refs["uncoded_own_prec"] = [k for k, v in bpx.PREC_NAMES.items() if v == ref_prec][0]
         if prec_name == "f32":
             torch.backends.cuda.matmul.allow_tf32 = False
@@ -232,18 +272,14 @@ def run_single(args):
         Ct = torch.empty((w.M, w.N), dtype=X.dtype, device=dev)
         for _ in range(3):
             torch.matmul(X, Y, out=Ct)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(args.steps):
-            torch.matmul(X, Y, out=Ct)
-        torch.cuda.synchronize()
-        refs["uncoded_torch_tflops"] = useful / ((time.perf_counter() - t1) / args.steps) / 1e12
+        refs["uncoded_torch_tflops"] = useful / (graph_ms(
+            torch, lambda: torch.matmul(X, Y, out=Ct), args.steps) * 1e-3) / 1e12
         refs["uncoded_torch_prec"] = tprec
         refs["frac_of_uncoded_best"] = value / max(refs["uncoded_own_tflops"],
                                                    refs["uncoded_torch_tflops"])
         refs["frac_of_uncoded_own"] = value / refs["uncoded_own_tflops"]
 
-    hbm = hbm_kernels(torch, bpx, plan, code, Ad, Cd, ws, w, info, args.steps, two_d)
+    hbm = hbm_kernels(torch, bpx, plan, code, Ad, Bd, Cd, ws, w, info, args.steps, two_d)
 
     n_comp = info["n_computed"]
     gemm_flops = 2.0 * Mb * w.K * w.N * n_comp
@@ -262,14 +298,18 @@ def run_single(args):
         f32_kernel = ("coded_gemm_2d_wide_kernel (256x256 tiles of block products, symbols "
                       "dealt by decreasing passes)" if full else
                       "coded_gemm_2d_kernel (64x128 tiles of block products)")
+    elif fused:
+        f32_kernel = ("fused_f32_kernel (coded products of 16-row tiles of every block and "
+                      "the peel in LDS, one launch)")
     elif Mb % 256 == 0 and w.N % 256 == 0 and w.K % 32 == 0 and w.M % Mb == 0:
         f32_kernel = ("coded_gemm_f32_wide_kernel<4,2> (full rounds of 256x256 tiles; a short "
                       "last round split along K + splitk_reduce_kernel, or as "
                       "coded_gemm_f32_kernel<64,128,32,2> sub-tiles), one call")
     else:
         f32_kernel = "coded_gemm_f32_kernel<64,128,32,2>"
-    kernel = {"f32": f32_kernel, "bf16": "split_b + coded_gemm_bf16_kernel",
-              "bf16x3": "split_b + coded_gemm_bf16_kernel",
+    bf16_kernel = ("fused_bf16_kernel (coded products and peel, one launch)" if fused else
+                   "split_b + coded_gemm_bf16_flat_kernel, one call")
+    kernel = {"f32": f32_kernel, "bf16": bf16_kernel, "bf16x3": bf16_kernel,
               "fp8": "quant_b + quant_a + coded_gemm_fp8_wide_kernel, one call",
               "fp8x2": "quant_b + quant_a + coded_gemm_fp8_wide_kernel, one call"}[prec_name]
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK[prec_name],
@@ -288,8 +328,9 @@ def run_single(args):
                 # arrival pattern, outside the timed region; with it per step:
                 "ms_per_step_incl_plan": ms + plan_us * 1e-3,
                 "value_incl_plan": useful / ((ms + plan_us * 1e-3) * 1e-3) / 1e12,
-                "times_ms": {"coded_gemm_call": gemm_ms, "peel": peel_ms,
-                             "plan_host_us": plan_us, "code_build_s": code_s},
+                "timing": "HIP graph replay of each step (and of each reference)",
+                "times_ms": {("fused_call" if fused else "coded_gemm_call"): gemm_ms,
+                             "peel": peel_ms, "plan_host_us": plan_us, "code_build_s": code_s},
                 "roofline": roofline, "hbm": hbm})
     out.update(refs)
     out["latency_model"] = latency_model(bpx, code, w, prec, gemm_ms, n_comp, hbm, refs, spec)
@@ -347,14 +388,17 @@ def latency_model(bpx, code, w, prec, gemm_ms, n_comp, hbm, refs, spec, samples=
     return res
 
 
-def hbm_kernels(torch, bpx, plan, code, Ad, Cd, ws, w, info, steps, two_d=False):
+def hbm_kernels(torch, bpx, plan, code, Ad, Bd, Cd, ws, w, info, steps, two_d=False):
     """Achieved HBM GB/s of the two streaming kernels: the standalone encode
-    (bpx_encode) and the peel, each as algorithmic bytes / event time."""
+    (bpx_encode) and the peel, each as algorithmic bytes / event time.  (A
+    plan that takes the fused form runs neither in its step; they are
+    measured on the same plan for reference.)"""
     sch = plan.schedule()
     col_ptr, sym_ptr, sym_data = code.csr()
     Mb, K, N, M = info["Mb"], w.K, w.N, w.M
     from paper_1904_11563_amd.latency import peel_bytes
     rd, wr = peel_bytes(plan, M, N)
+    bpx.coded_gemm(plan, Ad, Bd, Cd, ws)   # the peel below reads these products
     peel_ms = timed(torch, lambda: bpx.peel_decode(plan, ws, Cd), steps)
     res = {"peak_GBps": 8000.0}
     legs = [("peel", rd + wr, peel_ms)]
@@ -451,20 +495,7 @@ def run_batch(args):
 
     useful = sum(2.0 * M * K * N for (M, K, N, _) in shapes)
 
-    def capture(gr):
-        graph = torch.cuda.CUDAGraph()
-        s = torch.cuda.Stream()
-        s.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(s):
-            gr.launch()          # warm (not captured)
-            torch.cuda.synchronize()
-            with torch.cuda.graph(graph, stream=s):
-                gr.launch()
-        torch.cuda.current_stream().wait_stream(s)
-        torch.cuda.synchronize()
-        return graph
-
-    graph = capture(group)
+    graph = capture(torch, group.launch)
     for _ in range(args.warmup):
         graph.replay()
     torch.cuda.synchronize()
@@ -496,7 +527,7 @@ def run_batch(args):
 
     refs = {}
     if not args.no_ref:
-        ugraph = capture(ugroup)
+        ugraph = capture(torch, ugroup.launch)
         for _ in range(3):
             ugraph.replay()
         torch.cuda.synchronize()

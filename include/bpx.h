@@ -281,10 +281,41 @@ bpx_status bpx_coded_gemm(bpx_plan* plan, const float* A, int64_t lda, const flo
 bpx_status bpx_peel_decode(bpx_plan* plan, const void* ws, size_t ws_bytes, float* C,
                            int64_t ldc, bpx_stream stream);
 
-/* bpx_coded_gemm followed by bpx_peel_decode on the same stream. */
+/* The whole coded product: bpx_coded_gemm followed by bpx_peel_decode on the
+ * same stream, or, for small products, one launch with the peel fused into
+ * the GEMM epilogue (the BP decoder of Sec. I-A applies the same release
+ * program to every element, so a workgroup that owns one 16-row tile of
+ * every data block computes that tile of every computed coded product,
+ * keeps the releasers' tiles in LDS and peels them there; the coded
+ * products never reach memory and ws is not used).  The fused form runs
+ * row-block F32 / BF16 / BF16x3 plans whose workgroup fits in LDS (the
+ * whole K extent of a 16..64-column strip of B is staged on chip), by
+ * default when the computed symbols hold at most 2^31 multiply-adds
+ * (bpx_set_fused_peel).  Both forms compute the same values in the same
+ * order of operations within each product: results match the two-launch
+ * path. */
 bpx_status bpx_coded_matmul(bpx_plan* plan, const float* A, int64_t lda, const float* B,
                             int64_t ldb, float* C, int64_t ldc, void* ws, size_t ws_bytes,
                             bpx_stream stream);
+
+/* When bpx_coded_matmul takes the fused form:
+ * 0 never, 1 for small products (the default), 2 whenever it fits.
+ * Process-wide, like the tile settings. */
+bpx_status bpx_set_fused_peel(int32_t mode);
+
+/* *fused = 1 if bpx_coded_matmul takes the fused form for this plan with
+ * dense operands (lda = K, ldb = ldc = N) under the current mode on the
+ * current device, else 0. */
+bpx_status bpx_plan_fused(bpx_plan* plan, int32_t* fused);
+
+/* The fused form's peel program (read-only, owned by the plan): steps in
+ * the bpx_plan_peel_program record format, but with src = the LDS Y tile
+ * that holds the releaser's product and write = 1 for every recovered
+ * block; ytile[i] is the Y tile of the i-th computed symbol (ascending g),
+ * -1 if it releases nothing.  Slots as in bpx_plan_peel_program. */
+bpx_status bpx_plan_fused_program(const bpx_plan* plan, const int32_t** steps, int32_t* n_steps,
+                                  const int32_t** subs, int32_t* n_subs, const int32_t** ytile,
+                                  int32_t* n_ytiles);
 
 /* ------------------------------------------------------------- groups -- */
 

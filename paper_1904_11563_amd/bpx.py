@@ -47,10 +47,11 @@ EXPORTS = [
     "bpx_plan_schedule", "bpx_plan_peel_program", "bpx_plan_workspace_bytes",
     "bpx_plan_workspace_layout",
     "bpx_plan_upload", "bpx_plan_free", "bpx_encode", "bpx_coded_gemm", "bpx_peel_decode",
-    "bpx_coded_matmul", "bpx_coded_matmul_grouped", "bpx_group_workspace_bytes",
+    "bpx_coded_matmul", "bpx_coded_matmul_grouped",
+    "bpx_group_workspace_bytes",
     "bpx_group_create", "bpx_group_launch", "bpx_group_launch_phase", "bpx_group_free",
     "bpx_tile_count", "bpx_set_tile_order", "bpx_set_tile_table", "bpx_force_tile",
-    "bpx_last_error",
+    "bpx_set_fused_peel", "bpx_plan_fused", "bpx_plan_fused_program", "bpx_last_error",
 ]
 
 
@@ -103,6 +104,10 @@ _sig = {
     "bpx_set_tile_table": (C.c_int, [_i32p, C.c_int32]),
     "bpx_force_tile": (C.c_int, [C.c_int32]),
     "bpx_set_tile_order": (C.c_int, [C.c_int32]),
+    "bpx_set_fused_peel": (C.c_int, [C.c_int32]),
+    "bpx_plan_fused": (C.c_int, [_p, _i32p]),
+    "bpx_plan_fused_program": (C.c_int, [_p, C.POINTER(_i32p), _i32p, C.POINTER(_i32p), _i32p,
+                                         C.POINTER(_i32p), _i32p]),
     "bpx_last_error": (C.c_char_p, []),
 }
 for _name, (_res, _args) in _sig.items():
@@ -291,6 +296,26 @@ class Plan:
         subs = np.ctypeslib.as_array(sb, shape=(ns.value,)).copy() if ns.value else np.zeros(0, np.int32)
         return {"steps": steps, "subs": subs, "n_slots": nsl.value}
 
+    def fused(self):
+        """Whether coded_matmul takes the fused form (one launch) for this plan."""
+        v = C.c_int32()
+        _check(_lib.bpx_plan_fused(self._h, C.byref(v)))
+        return bool(v.value)
+
+    def fused_program(self):
+        """The fused form's peel program: {"steps": int32 [n, 9] (PEEL_FIELDS,
+        src = Y tile), "subs", "ytile" (per computed symbol), "n_ytiles"}."""
+        st, sb, yt = _i32p(), _i32p(), _i32p()
+        n, ns, ny = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(_lib.bpx_plan_fused_program(self._h, C.byref(st), C.byref(n), C.byref(sb),
+                                           C.byref(ns), C.byref(yt), C.byref(ny)))
+        nc = self.info()["n_computed"]
+        steps = (np.ctypeslib.as_array(st, shape=(n.value * 9,)).copy().reshape(n.value, 9)
+                 if n.value else np.zeros((0, 9), np.int32))
+        subs = np.ctypeslib.as_array(sb, shape=(ns.value,)).copy() if ns.value else np.zeros(0, np.int32)
+        ytile = np.ctypeslib.as_array(yt, shape=(nc,)).copy() if nc and n.value else np.zeros(0, np.int32)
+        return {"steps": steps, "subs": subs, "ytile": ytile, "n_ytiles": ny.value}
+
     def workspace_bytes(self):
         ws, enc = C.c_size_t(), C.c_size_t()
         _check(_lib.bpx_plan_workspace_bytes(self._h, C.byref(ws), C.byref(enc)))
@@ -463,3 +488,9 @@ def set_tile_order(group_m):
 
 def force_tile(t):
     _check(_lib.bpx_force_tile(t))
+
+
+def set_fused_peel(mode):
+    """0: never fuse the peel into the GEMM; 1: small products (default);
+    2: whenever the fused form fits."""
+    _check(_lib.bpx_set_fused_peel(mode))

@@ -14,6 +14,7 @@ namespace bpx {
 
 namespace {
 thread_local std::string g_error;
+int32_t g_fused_mode = 1;  // 0 never, 1 small products, 2 whenever it fits
 int32_t g_force_tile = -1;
 int32_t g_group_m = 2;
 int32_t g_tile_table[8 * 8 * 8 * 5];
@@ -93,12 +94,21 @@ bpx_status upload(bpx_plan* plan) {
   const size_t b1 = bytes_of(plan->gemm_ids.size(), 4);
   const size_t b2 = bytes_of(plan->steps.size(), sizeof(PeelStep));
   const size_t b3 = bytes_of(plan->step_subs.size(), 4);
-  const size_t total = std::max<size_t>(b0 + b1 + b2 + b3, 256);
+  const size_t b4 = bytes_of(plan->fused_steps.size(), sizeof(PeelStep));
+  const size_t b5 = bytes_of(plan->fused_subs.size(), 4);
+  const size_t b6 = bytes_of(plan->fused_ytile.size(), 4);
+  const size_t total = std::max<size_t>(b0 + b1 + b2 + b3 + b4 + b5 + b6, 256);
   std::string host(total, '\0');
   std::memcpy(&host[0], plan->gemm_syms.data(), plan->gemm_syms.size() * 4);
   std::memcpy(&host[b0], plan->gemm_ids.data(), plan->gemm_ids.size() * 4);
   std::memcpy(&host[b0 + b1], plan->steps.data(), plan->steps.size() * sizeof(PeelStep));
   std::memcpy(&host[b0 + b1 + b2], plan->step_subs.data(), plan->step_subs.size() * 4);
+  std::memcpy(&host[b0 + b1 + b2 + b3], plan->fused_steps.data(),
+              plan->fused_steps.size() * sizeof(PeelStep));
+  std::memcpy(&host[b0 + b1 + b2 + b3 + b4], plan->fused_subs.data(),
+              plan->fused_subs.size() * 4);
+  std::memcpy(&host[b0 + b1 + b2 + b3 + b4 + b5], plan->fused_ytile.data(),
+              plan->fused_ytile.size() * 4);
   void* d = nullptr;
   e = hipMalloc(&d, total);
   if (e != hipSuccess) return hip_fail(e, "hipMalloc(plan tables)");
@@ -114,6 +124,9 @@ bpx_status upload(bpx_plan* plan) {
   plan->d_gemm_ids = reinterpret_cast<const int32_t*>(base + b0);
   plan->d_steps = reinterpret_cast<const PeelStep*>(base + b0 + b1);
   plan->d_step_subs = reinterpret_cast<const int32_t*>(base + b0 + b1 + b2);
+  plan->d_fused_steps = reinterpret_cast<const PeelStep*>(base + b0 + b1 + b2 + b3);
+  plan->d_fused_subs = reinterpret_cast<const int32_t*>(base + b0 + b1 + b2 + b3 + b4);
+  plan->d_fused_ytile = reinterpret_cast<const int32_t*>(base + b0 + b1 + b2 + b3 + b4 + b5);
   return BPX_OK;
 }
 
@@ -225,6 +238,53 @@ bpx_status gemm_impl(bpx_plan* plan, const float* A, int64_t lda, const float* B
   }
   if (e != hipSuccess) return hip_fail(e, "coded gemm launch");
   return BPX_OK;
+}
+
+// The fused form (one launch, peel in the GEMM epilogue): row-block plans of
+// F32 / BF16 / BF16x3 whose workgroup LDS fits; in the default mode only
+// products small enough that launches and latency dominate the two-launch
+// path (at most 2^31 multiply-adds over the computed symbols, e.g. 512^3
+// with eight symbols is 2^27).
+bool fused_params(bpx_plan* plan, const float* A, int64_t lda, const float* B, int64_t ldb,
+                  float* C, int64_t ldc, FusedParams* f) {
+  if (g_fused_mode == 0 || plan->grid != 1 || plan->fused_steps.empty()) return false;
+  const double macs = (double)plan->computed.size() * (double)plan->Mb * (double)plan->K *
+                      (double)plan->N;
+  if (g_fused_mode == 1 && macs > 2147483648.0) return false;
+  *f = FusedParams{};
+  f->A = A;
+  f->lda = lda;
+  f->B = B;
+  f->ldb = ldb;
+  f->C = C;
+  f->ldc = ldc;
+  f->M = plan->M;
+  f->K = plan->K;
+  f->N = plan->N;
+  f->Mb = plan->Mb;
+  f->syms = plan->d_gemm_syms;
+  f->ids = plan->d_gemm_ids;
+  f->ytile = plan->d_fused_ytile;
+  f->n_sym = (int32_t)plan->computed.size();
+  f->n_ytiles = plan->n_ytiles;
+  f->n_ids = (int32_t)plan->gemm_ids.size();
+  f->off_ids = (int32_t)(plan->d_gemm_ids - plan->d_gemm_syms);
+  f->off_steps = (int32_t)(reinterpret_cast<const int32_t*>(plan->d_fused_steps) -
+                           plan->d_gemm_syms);
+  f->off_subs = (int32_t)(plan->d_fused_subs - plan->d_gemm_syms);
+  f->off_ytile = (int32_t)(plan->d_fused_ytile - plan->d_gemm_syms);
+  f->blob_words = f->off_ytile + (int32_t)plan->fused_ytile.size();
+  f->steps = plan->d_fused_steps;
+  f->subs = plan->d_fused_subs;
+  f->nsteps = (int32_t)plan->fused_steps.size();
+  f->nsubs = (int32_t)plan->fused_subs.size();
+  f->nslots = plan->n_lds_slots;
+  f->prec = plan->prec;
+  f->kb = plan->code.kb();
+  f->max_deg = 0;
+  for (size_t i = 0; i < plan->computed.size(); ++i)
+    f->max_deg = std::max(f->max_deg, plan->gemm_syms[4 * i + 1]);
+  return fused_configure(f);
 }
 
 bpx_status peel_impl(bpx_plan* plan, const void* ws, size_t ws_bytes, float* C, int64_t ldc,
@@ -778,6 +838,19 @@ bpx_status bpx_coded_matmul(bpx_plan* plan, const float* A, int64_t lda, const f
   bpx_status st = check_device_call(plan);
   if (st != BPX_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  FusedParams f;
+  if (fused_params(plan, A, lda, B, ldb, C, ldc, &f)) {
+    // same argument contract as the two-launch form (the caller cannot
+    // tell which form runs), though the fused launch leaves ws untouched
+    if ((st = check_matrix(A, lda, plan->K, "A")) != BPX_OK) return st;
+    if ((st = check_matrix(B, ldb, plan->N, "B")) != BPX_OK) return st;
+    if ((st = check_matrix(C, ldc, plan->N, "C")) != BPX_OK) return st;
+    if (plan->ws_bytes() > 0 && (!ws || ws_bytes < plan->ws_bytes() || ((uintptr_t)ws & 255u)))
+      return fail(BPX_E_INVALID, "workspace missing, not 256-byte aligned or too small");
+    const hipError_t e = launch_fused(f, s);
+    if (e != hipSuccess) return hip_fail(e, "fused coded product launch");
+    return BPX_OK;
+  }
   st = gemm_impl(plan, A, lda, B, ldb, C, ldc, ws, ws_bytes, s);
   if (st != BPX_OK) return st;
   return peel_impl(plan, ws, ws_bytes, C, ldc, s);
@@ -856,6 +929,35 @@ bpx_status bpx_set_tile_table(const int32_t* table, int32_t n_entries) {
 bpx_status bpx_set_tile_order(int32_t group_m) {
   if (group_m < 1 || group_m > 64) return fail(BPX_E_INVALID, "group_m must be in [1, 64]");
   g_group_m = group_m;
+  return BPX_OK;
+}
+
+bpx_status bpx_set_fused_peel(int32_t mode) {
+  if (mode < 0 || mode > 2) return fail(BPX_E_INVALID, "fused-peel mode must be 0, 1 or 2");
+  g_fused_mode = mode;
+  return BPX_OK;
+}
+
+bpx_status bpx_plan_fused(bpx_plan* plan, int32_t* fused) {
+  if (!plan || !fused) return fail(BPX_E_INVALID, "null argument");
+  FusedParams f;
+  *fused = plan->decodable &&
+                   fused_params(plan, nullptr, plan->K, nullptr, plan->N, nullptr, plan->N, &f)
+               ? 1
+               : 0;
+  return BPX_OK;
+}
+
+bpx_status bpx_plan_fused_program(const bpx_plan* plan, const int32_t** steps, int32_t* n_steps,
+                                  const int32_t** subs, int32_t* n_subs, const int32_t** ytile,
+                                  int32_t* n_ytiles) {
+  if (!plan) return fail(BPX_E_INVALID, "null plan");
+  if (steps) *steps = reinterpret_cast<const int32_t*>(plan->fused_steps.data());
+  if (n_steps) *n_steps = (int32_t)plan->fused_steps.size();
+  if (subs) *subs = plan->fused_subs.data();
+  if (n_subs) *n_subs = (int32_t)plan->fused_subs.size();
+  if (ytile) *ytile = plan->fused_ytile.data();
+  if (n_ytiles) *n_ytiles = plan->n_ytiles;
   return BPX_OK;
 }
 

@@ -66,6 +66,13 @@ struct bpx_plan {
   std::vector<int32_t> gemm_syms;
   std::vector<int32_t> gemm_ids;
 
+  // Fused peel program (every recovered block has a step; src is the
+  // releaser's LDS Y tile) and, per GEMM-table entry, its Y tile or -1.
+  std::vector<PeelStep> fused_steps;
+  std::vector<int32_t> fused_subs;
+  std::vector<int32_t> fused_ytile;
+  int32_t n_ytiles = 0;
+
   // device copies
   void* dev_block = nullptr;
   int32_t dev_id = -1;
@@ -73,6 +80,9 @@ struct bpx_plan {
   const int32_t* d_gemm_ids = nullptr;
   const PeelStep* d_steps = nullptr;
   const int32_t* d_step_subs = nullptr;
+  const PeelStep* d_fused_steps = nullptr;
+  const int32_t* d_fused_subs = nullptr;
+  const int32_t* d_fused_ytile = nullptr;
 
   size_t y_bytes() const { return (size_t)n_yslots * (size_t)Mb * (size_t)Nb * sizeof(float); }
   // K rounded up to the BF16 kernels' 32-wide k step

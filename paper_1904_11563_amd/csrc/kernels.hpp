@@ -94,7 +94,7 @@ struct PeelParams {
 };
 // Bytes of LDS a peel workgroup holds besides its slots: the step program
 // (steps, then subs), staged once per workgroup.
-inline size_t peel_program_bytes(int32_t nsteps, int32_t nsubs) {
+__host__ __device__ inline size_t peel_program_bytes(int32_t nsteps, int32_t nsubs) {
   return ((size_t)nsteps * sizeof(PeelStep) + (size_t)nsubs * 4 + 15) / 16 * 16;
 }
 
@@ -166,6 +166,51 @@ int64_t peel_grouped_grid(int64_t total_blocks, int32_t max_slots, size_t max_pr
 hipError_t launch_peel_grouped(const GroupDesc* d, const int64_t* pstart, const int32_t* pmap,
                                const int64_t* wstart, int64_t grid, int32_t max_slots,
                                size_t max_program, hipStream_t stream);
+
+// ------------------------------------------------------ fused peel --
+// One launch computing every computed symbol's product for a 16 x BN output
+// tile of all data blocks and peeling it in LDS (see fused.hip).  syms/ids
+// as in GemmParams (GEMM-table order); ytile[i]: the LDS Y tile of computed
+// symbol i, or -1 if it releases nothing; steps/subs: the fused peel
+// program (src = Y tile of the releaser, every recovered block written).
+struct FusedParams {
+  const float* A;
+  int64_t lda;
+  const float* B;
+  int64_t ldb;
+  float* C;
+  int64_t ldc;
+  int64_t M, K, N, Mb;
+  const int32_t* syms;
+  const int32_t* ids;
+  const int32_t* ytile;
+  int32_t n_sym;
+  int32_t n_ytiles;
+  int32_t n_ids;  // length of ids
+  // The plan's device tables are one block; the kernel copies the span from
+  // syms to the end of ytile to LDS in one pass (word offsets from syms).
+  int32_t blob_words;
+  int32_t off_ids, off_steps, off_subs, off_ytile;
+  const PeelStep* steps;
+  const int32_t* subs;
+  int32_t nsteps;
+  int32_t nsubs;
+  int32_t nslots;
+  int32_t prec;
+  // set by fused_configure
+  int32_t jn;  // column tile = 16 jn
+  int32_t tiles_m, tiles_n;
+  int32_t kb;       // data blocks
+  int32_t max_deg;  // largest degree of a computed symbol
+  int32_t kg;       // k per A-stage group (32 or 64)
+  int32_t pad;
+  int64_t kp;  // K rounded up to the k group
+};
+// Picks the tile width and checks that the workgroup's LDS fits; false if
+// the fused form cannot run this product (precision or LDS).
+bool fused_configure(FusedParams* p);
+size_t fused_lds_bytes(const FusedParams& p);
+hipError_t launch_fused(const FusedParams& p, hipStream_t stream);
 
 hipError_t launch_quant_a(const Fp8Params& p, hipStream_t stream);
 hipError_t launch_quant_b(const Fp8Params& p, hipStream_t stream);

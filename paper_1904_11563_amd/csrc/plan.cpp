@@ -241,6 +241,10 @@ int make_plan(const bpx_code& code, const int32_t* arrival, int32_t n_arrival, i
   plan->steps.clear();
   plan->step_subs.clear();
   plan->n_lds_slots = 0;
+  plan->fused_steps.clear();
+  plan->fused_subs.clear();
+  plan->fused_ytile.clear();
+  plan->n_ytiles = 0;
   if (ok) {
     std::vector<int32_t> order(kb);
     std::iota(order.begin(), order.end(), 0);
@@ -284,6 +288,36 @@ int make_plan(const bpx_code& code, const int32_t* arrival, int32_t n_arrival, i
       auto it = std::lower_bound(plan->computed.begin(), plan->computed.end(), g);
       return plan->dest[it - plan->computed.begin()];
     };
+    // Fused form: the releasers' products stay in LDS Y tiles, numbered in
+    // GEMM-table order; every recovered block gets a step and is written.
+    std::vector<int32_t> ytile_of_g(code.n_sym(), -1);
+    plan->fused_ytile.clear();
+    plan->n_ytiles = 0;
+    {
+      std::vector<char> is_rel(code.n_sym(), 0);
+      for (int32_t s = 0; s < kb; ++s)
+        if (plan->releaser[s] >= 0) is_rel[plan->releaser[s]] = 1;
+      for (size_t t = 0; t < plan->gemm_syms.size() / 4; ++t) {
+        const int32_t g = plan->gemm_syms[4 * t + 3];
+        if (is_rel[g] && ytile_of_g[g] < 0) ytile_of_g[g] = plan->n_ytiles++;
+        plan->fused_ytile.push_back(is_rel[g] ? ytile_of_g[g] : -1);
+      }
+    }
+    for (int32_t s : order) {
+      PeelStep st{};
+      st.s = s;
+      st.src = ytile_of_g[plan->releaser[s]];
+      st.nsub = plan->sub_ptr[s + 1] - plan->sub_ptr[s];
+      st.sub_off = (int32_t)plan->fused_subs.size();
+      st.f64 = plan->depth[s] > 4 ? 1 : 0;
+      st.slot = slot[s];
+      st.write = 1;
+      st.brow = s / plan->grid;
+      st.bcol = s % plan->grid;
+      for (int32_t e = plan->sub_ptr[s]; e < plan->sub_ptr[s + 1]; ++e)
+        plan->fused_subs.push_back(slot[plan->sub_data[e]]);
+      plan->fused_steps.push_back(st);
+    }
     for (int32_t s : order) {
       const int32_t g = plan->releaser[s];
       const int32_t dst = dest_of(g);

@@ -106,6 +106,16 @@ def code642():
 # ------------------------------------------------------------- small, exact --
 
 def test_every_erasure_pair_small_code_integer_exact():
+    # the two-launch path (coded GEMM + streaming peel); the fused form has
+    # its own tests
+    bpx.set_fused_peel(0)
+    try:
+        _every_erasure_pair_small_code_integer_exact()
+    finally:
+        bpx.set_fused_peel(1)
+
+
+def _every_erasure_pair_small_code_integer_exact():
     code = code642()
     oc = oracle_of(code)
     M, K, N = 517, 260, 300            # ragged in every dimension

@@ -113,6 +113,7 @@ def _compare(lib_code, ocode, arrival, n_lost, mode, M=100, K=8, N=8):
             slot += 1
     if want.decodable:
         _run_peel_program(plan, ocode, sch)
+        _run_fused_program(plan, ocode, sch)
     return plan
 
 
@@ -150,6 +151,44 @@ def _run_peel_program(plan, ocode, sch, width=3, seed=5):
             xs[st["slot"]] = x
         if st["write"]:
             C[st["s"]] = x
+    assert np.array_equal(C, v)
+
+
+def _run_fused_program(plan, ocode, sch, width=3, seed=6):
+    """Execute the fused form's peel program on the host as the fused kernel
+    does per element: every computed symbol's product Y_g lands in its LDS Y
+    tile (ytile >= 0) or is dropped; each step takes the releaser's Y tile,
+    subtracts its slots, keeps the result in its slot and writes C.  Every
+    block must come out exactly and be written by exactly one step."""
+    rng = np.random.default_rng(seed)
+    kb = ocode.kb
+    v = rng.integers(-8, 9, size=(kb, width)).astype(np.float64)
+    sym = {g: d for g, _, d in ocode.symbols()}
+    fp = plan.fused_program()
+    computed = sch["computed"].tolist()
+    assert len(fp["ytile"]) == len(computed)
+    yt = np.full((max(fp["n_ytiles"], 1), width), np.nan)
+    releasers = set(sch["releaser"].tolist())
+    for g, t in zip(computed, fp["ytile"].tolist()):
+        assert (t >= 0) == (g in releasers)
+        if t >= 0:
+            yt[t] = v[list(sym[g])].sum(axis=0)
+    prog = plan.peel_program()
+    xs = np.full((max(prog["n_slots"], 1), width), np.nan)
+    C = np.full((kb, width), np.nan)
+    written = []
+    F = bpx.Plan.PEEL_FIELDS
+    for row in fp["steps"]:
+        st = dict(zip(F, row.tolist()))
+        x = yt[st["src"]].copy()
+        for u in range(st["nsub"]):
+            x -= xs[fp["subs"][st["sub_off"] + u]]
+        if st["slot"] >= 0:
+            xs[st["slot"]] = x
+        assert st["write"] == 1
+        C[st["s"]] = x
+        written.append(st["s"])
+    assert sorted(written) == list(range(kb))
     assert np.array_equal(C, v)
 
 
