@@ -298,7 +298,7 @@ bpx_status bpx_coded_matmul(bpx_plan* plan, const float* A, int64_t lda, const f
                             int64_t ldb, float* C, int64_t ldc, void* ws, size_t ws_bytes,
                             bpx_stream stream);
 
-/* When bpx_coded_matmul takes the fused form:
+/* When bpx_coded_matmul (and bpx_coded_matmul_noalloc) take the fused form:
  * 0 never, 1 for small products (the default), 2 whenever it fits.
  * Process-wide, like the tile settings. */
 bpx_status bpx_set_fused_peel(int32_t mode);
@@ -316,6 +316,21 @@ bpx_status bpx_plan_fused(bpx_plan* plan, int32_t* fused);
 bpx_status bpx_plan_fused_program(const bpx_plan* plan, const int32_t** steps, int32_t* n_steps,
                                   const int32_t** subs, int32_t* n_subs, const int32_t** ytile,
                                   int32_t* n_ytiles);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product as bpx_coded_matmul, same kernels and results, with the workspace
+ * taken from a static device array of the library (32 MiB per GPU, held by
+ * every device that uses it until the process ends) instead of a caller
+ * buffer.  Allocates nothing: the plan's tables must already be on the
+ * current device (bpx_plan_upload), else BPX_E_INVALID; a plan whose
+ * workspace (bpx_plan_workspace_bytes) exceeds 32 MiB gets
+ * BPX_E_UNSUPPORTED.  Every call on one GPU shares that GPU's array, and
+ * nothing in it needs to start at zero (each call writes every byte it
+ * reads first): calls that overlap on one GPU (other streams, other
+ * threads) race and must be serialised by the caller. */
+bpx_status bpx_coded_matmul_noalloc(bpx_plan* plan, const float* A, int64_t lda, const float* B,
+                                    int64_t ldb, float* C, int64_t ldc, bpx_stream stream);
 
 /* ------------------------------------------------------------- groups -- */
 

@@ -47,7 +47,7 @@ EXPORTS = [
     "bpx_plan_schedule", "bpx_plan_peel_program", "bpx_plan_workspace_bytes",
     "bpx_plan_workspace_layout",
     "bpx_plan_upload", "bpx_plan_free", "bpx_encode", "bpx_coded_gemm", "bpx_peel_decode",
-    "bpx_coded_matmul", "bpx_coded_matmul_grouped",
+    "bpx_coded_matmul", "bpx_coded_matmul_noalloc", "bpx_coded_matmul_grouped",
     "bpx_group_workspace_bytes",
     "bpx_group_create", "bpx_group_launch", "bpx_group_launch_phase", "bpx_group_free",
     "bpx_tile_count", "bpx_set_tile_order", "bpx_set_tile_table", "bpx_force_tile",
@@ -92,6 +92,8 @@ _sig = {
     "bpx_peel_decode": (C.c_int, [_p, _p, C.c_size_t, _p, C.c_int64, _p]),
     "bpx_coded_matmul": (C.c_int, [_p, _p, C.c_int64, _p, C.c_int64, _p, C.c_int64, _p,
                                    C.c_size_t, _p]),
+    "bpx_coded_matmul_noalloc": (C.c_int, [_p, _p, C.c_int64, _p, C.c_int64, _p, C.c_int64,
+                                           _p]),
     "bpx_coded_matmul_grouped": (C.c_int, [C.POINTER(_p), C.POINTER(_p), C.POINTER(_p),
                                            C.POINTER(_p), C.c_int32, _p, C.c_size_t, _p]),
     "bpx_group_workspace_bytes": (C.c_int, [C.POINTER(_p), C.c_int32, C.POINTER(C.c_size_t)]),
@@ -416,6 +418,15 @@ def coded_matmul(plan: Plan, A, B, C_out, ws, stream=None):
     c, ldc = _mat(C_out, "C", (plan.M, plan.N))
     w, wb = _ws(ws)
     _check(_lib.bpx_coded_matmul(plan._h, a, lda, b, ldb, c, ldc, w, wb, _stream(stream)))
+
+
+def coded_matmul_noalloc(plan: Plan, A, B, C_out, stream=None):
+    """bpx_coded_matmul with the library's static scratch array as workspace
+    (the plan must have been uploaded; 32 MiB limit)."""
+    a, lda = _mat(A, "A", (plan.M, plan.K))
+    b, ldb = _mat(B, "B", (plan.K, plan.N))
+    c, ldc = _mat(C_out, "C", (plan.M, plan.N))
+    _check(_lib.bpx_coded_matmul_noalloc(plan._h, a, lda, b, ldb, c, ldc, _stream(stream)))
 
 
 def _group_operands(plans, As, Bs, Cs):

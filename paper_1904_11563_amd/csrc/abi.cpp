@@ -240,6 +240,36 @@ bpx_status gemm_impl(bpx_plan* plan, const float* A, int64_t lda, const float* B
   return BPX_OK;
 }
 
+// ------------------------------------------------------------ scratch --
+// Workspace of the no-allocation entry point: one static device array per
+// GPU (each device that loads the library holds its own copy until the
+// process ends).  In host code `scratch` is a host-side stand-in for the
+// symbol, not a device address: its device address is looked up once per
+// device with hipGetSymbolAddress and only that pointer is passed on.
+constexpr size_t kScratchBytes = (size_t)32 << 20;  // 32 MiB
+__device__ __attribute__((aligned(256))) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[64] = {nullptr};
+
+// Device address of this device's scratch array (looked up on first use).
+bpx_status scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= 64) return fail(BPX_E_UNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr || ((uintptr_t)ptr & 255u)) return fail(BPX_E_HIP, "scratch array misplaced");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return BPX_OK;
+}
+
 // The fused form (one launch, peel in the GEMM epilogue): row-block plans of
 // F32 / BF16 / BF16x3 whose workgroup LDS fits; in the default mode only
 // products small enough that launches and latency dominate the two-launch
@@ -854,6 +884,41 @@ bpx_status bpx_coded_matmul(bpx_plan* plan, const float* A, int64_t lda, const f
   st = gemm_impl(plan, A, lda, B, ldb, C, ldc, ws, ws_bytes, s);
   if (st != BPX_OK) return st;
   return peel_impl(plan, ws, ws_bytes, C, ldc, s);
+}
+
+bpx_status bpx_coded_matmul_noalloc(bpx_plan* plan, const float* A, int64_t lda, const float* B,
+                                    int64_t ldb, float* C, int64_t ldc, bpx_stream stream) {
+  if (!plan) return fail(BPX_E_INVALID, "null plan");
+  if (!plan->decodable) return fail(BPX_E_UNDECODABLE, "plan is not decodable");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  // the plan's tables must already be on this device: uploading allocates
+  if (!plan->dev_block || plan->dev_id != dev)
+    return fail(BPX_E_INVALID, "plan tables not uploaded to this device (call bpx_plan_upload)");
+  if (plan->K % 4 != 0) return fail(BPX_E_INVALID, "K must be a multiple of 4");
+  const size_t need = plan->ws_bytes();
+  if (need > kScratchBytes)
+    return fail(BPX_E_UNSUPPORTED, "plan needs " + std::to_string(need) +
+                                       " bytes of workspace; the scratch array holds " +
+                                       std::to_string(kScratchBytes));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  bpx_status st;
+  FusedParams f;
+  if (fused_params(plan, A, lda, B, ldb, C, ldc, &f)) {  // needs no workspace
+    if ((st = check_matrix(A, lda, plan->K, "A")) != BPX_OK) return st;
+    if ((st = check_matrix(B, ldb, plan->N, "B")) != BPX_OK) return st;
+    if ((st = check_matrix(C, ldc, plan->N, "C")) != BPX_OK) return st;
+    const hipError_t e = launch_fused(f, s);
+    if (e != hipSuccess) return hip_fail(e, "fused coded product launch");
+    return BPX_OK;
+  }
+  void* ws = nullptr;
+  st = scratch_address(&ws);
+  if (st != BPX_OK) return st;
+  st = gemm_impl(plan, A, lda, B, ldb, C, ldc, ws, kScratchBytes, s);
+  if (st != BPX_OK) return st;
+  return peel_impl(plan, ws, kScratchBytes, C, ldc, s);
 }
 
 bpx_status bpx_group_workspace_bytes(bpx_plan* const* plans, int32_t count, size_t* bytes) {

@@ -1,0 +1,92 @@
+"""The no-allocation entry point (bpx_coded_matmul_noalloc) against
+bpx_coded_matmul: same kernels, the workspace in the library's static
+scratch array instead of a caller buffer.  Two calls in a row on one GPU,
+the second with a smaller product, must each match the allocating entry
+point bit for bit (and integer operands must decode to A.B exactly)."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1904_11563_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_1904_11563_amd import bpx  # noqa: E402
+
+SCRATCH_BYTES = 32 << 20
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _code642():
+    s = inputs.CODE_642
+    return bpx.Code.search(s.n, s.k, s.b, s.sigma, s.seed, s.restarts, s.iters)
+
+
+def _pair(plan, A, B):
+    """(allocating result, no-allocation result) of one product, both on the
+    two-launch path (the fused form of small products uses no workspace)."""
+    Ad = torch.from_numpy(A).cuda()
+    Bd = torch.from_numpy(B).cuda()
+    M, N = A.shape[0], B.shape[1]
+    C0 = torch.full((M, N), float("nan"), device="cuda")
+    C1 = torch.full((M, N), float("nan"), device="cuda")
+    bpx.set_fused_peel(0)
+    try:
+        bpx.coded_matmul(plan, Ad, Bd, C0, bpx.alloc_workspace(plan))
+        bpx.coded_matmul_noalloc(plan, Ad, Bd, C1)
+    finally:
+        bpx.set_fused_peel(1)
+    torch.cuda.synchronize()
+    return C0.cpu().numpy(), C1.cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", [bpx.PREC_F32, bpx.PREC_BF16X3])
+def test_noalloc_matches_allocating_entry_point(prec):
+    code = _code642()
+    arrival, lost = inputs.erasure_arrival(0, 6, 2)
+    cases = [(512, 512, 512, 0), (200, 96, 136, 1)]   # second call: smaller, ragged
+    for M, K, N, seed in cases:
+        _say(f"noalloc prec={prec} M={M} K={K} N={N} seed={seed}")
+        plan = bpx.Plan(code, arrival, lost, bpx.MODE_ERASURE, M, K, N, prec)
+        assert plan.decodable
+        plan.upload()
+        assert plan.workspace_bytes()[0] <= SCRATCH_BYTES
+        # integer operands: every operation exact, the product must be A.B
+        A = inputs.integers(seed, inputs.TAG_A, (M, K))
+        B = inputs.integers(seed, inputs.TAG_B, (K, N))
+        C0, C1 = _pair(plan, A, B)
+        assert np.array_equal(C1.astype(np.float64), A.astype(np.float64) @ B)
+        assert np.array_equal(C0, C1)
+        # float operands: bit-identical to the allocating entry point
+        A = inputs.normal(seed, inputs.TAG_A, (M, K))
+        B = inputs.normal(seed, inputs.TAG_B, (K, N))
+        C0, C1 = _pair(plan, A, B)
+        assert not np.isnan(C1).any()
+        assert np.array_equal(C0, C1)
+
+
+def test_noalloc_rejects_what_it_cannot_serve():
+    code = _code642()
+    arrival, lost = inputs.erasure_arrival(0, 6, 2)
+    A = torch.zeros((64, 32), device="cuda")
+    B = torch.zeros((32, 64), device="cuda")
+    C = torch.zeros((64, 64), device="cuda")
+    plan = bpx.Plan(code, arrival, lost, bpx.MODE_ERASURE, 64, 32, 64)
+    with pytest.raises(bpx.BpxError) as e:          # tables not uploaded: would allocate
+        bpx.coded_matmul_noalloc(plan, A, B, C)
+    assert e.value.status == bpx.E_INVALID
+    # a plan whose workspace exceeds the scratch array (checked before any launch)
+    big = bpx.Plan(code, arrival, lost, bpx.MODE_FULL, 8192, 32, 8192)
+    assert big.workspace_bytes()[0] > SCRATCH_BYTES
+    big.upload()
+    Ab = torch.zeros((8192, 32), device="cuda")
+    Bb = torch.zeros((32, 8192), device="cuda")
+    Cb = torch.zeros((8192, 8192), device="cuda")
+    with pytest.raises(bpx.BpxError) as e:
+        bpx.coded_matmul_noalloc(big, Ab, Bb, Cb)
+    assert e.value.status == bpx.E_UNSUPPORTED
