@@ -139,7 +139,7 @@ def graph_ms(torch, fn, steps, warmup=3):
 def build_code(bpx, spec):
     if spec.kind == "search":
         return bpx.Code.search(spec.n, spec.k, spec.b, spec.sigma, spec.seed, spec.restarts,
-                               spec.iters)
+                               spec.iters, walk=spec.walk)
     return bpx.Code.mojette(spec.k, spec.b, spec.n, spec.qe)
 
 
@@ -563,7 +563,7 @@ def run_batch(args):
            "mean_prefix_overhead": float(np.mean([m["n_computed"] * 1.0 /
                                                   (2 * s[3]) for m, s in zip(meta, shapes)])),
            "tile_table": (f"forced {args.tile}" if args.tile >= 0 else
-                          "autotuned" if tuned else "default"), "graph": "hipGraph replay",
+                          f"autotuner table: {tuned}"), "graph": "hipGraph replay",
            "parallelism": "none (1 GPU)"}
     out = header(args, value, ms, prec_name, cfg)
     out.update({"rel_err": rel_err, "rel_err_sample": "8 rows x all columns of every product",

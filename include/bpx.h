@@ -92,6 +92,11 @@ typedef struct {
   int32_t mojette_qe;  /* MOJETTE: 0 = Construction A (q = 1),
                           >= 1 = Construction B (q = 2^qe, odd p)            */
   uint64_t seed;       /* ARRAY_SEARCH: SplitMix64 seed                       */
+  int32_t walk;        /* ARRAY_SEARCH: 0 = hill-climb (keep a change when the
+                          whole objective does not get worse), 1 = plateau
+                          walk (keep it when (failing subsets, all-columns
+                          flag) does not get worse; return the best code seen) */
+  int32_t reserved;    /* must be 0                                           */
 } bpx_code_params;
 
 typedef struct bpx_code bpx_code;
@@ -102,12 +107,13 @@ typedef struct ihipStream_t* bpx_stream; /* a hipStream_t; NULL = null stream */
 
 /* Build a code (host, integer only).  Symbols are numbered column by column
  * (g = symbols in earlier columns + row); data ids of a symbol are sorted.
- * ARRAY_SEARCH: a hill-climb over random codes driven by one SplitMix64(seed)
- *   stream, minimising (failing k-column subsets, all-columns-fail flag,
- *   unrecovered ids summed over failing subsets, peeling rounds summed over
- *   peelable subsets, total degree); the paper gives no general construction
- *   for array BP-XOR codes (Sec. III-A/B) so the code is searched.  Needs
- *   k*b <= 64.  Cost grows with restarts * iters * C(n, k).
+ * ARRAY_SEARCH: a local search over random codes driven by one
+ *   SplitMix64(seed) stream, minimising (failing k-column subsets,
+ *   all-columns-fail flag, unrecovered ids summed over failing subsets,
+ *   peeling rounds summed over peelable subsets, total degree), as a
+ *   hill-climb or a plateau walk (walk); the paper gives no general
+ *   construction for array BP-XOR codes (Sec. III-A/B) so the code is
+ *   searched.  Needs k*b <= 64.  Cost grows with restarts * iters * C(n, k).
  * TABLE1 / TABLE3: the worked codes of Table I / Table III; v_i -> id i-1.
  * MOJETTE: n projections over the k x b grid, ascending p; bin of cell
  *   (z, l) given by Eq. (moj1); data id of (z, l) is l*b + z; empty bins keep

@@ -358,16 +358,21 @@ def search_objective(cols_masks, k: int, full: int):
 
 
 def array_search(n: int, k: int, b: int, sigma: int, seed: int,
-                 restarts: int, iters: int) -> Code:
+                 restarts: int, iters: int, walk: int = 0) -> Code:
     """Deterministic search for an [n, k, ., b] array BP-XOR code.
 
     One SplitMix64(seed) stream drives everything.  Each restart draws the
     n*b symbols in ascending g (a symbol: degree 1 + draw mod sigma, then
     distinct data ids by rejection, each id = draw mod kb).  Each iteration
-    draws a position g = draw mod (n*b) and a fresh symbol, and keeps the
-    change when the objective (U, F, L, D, S) does not get worse
-    (lexicographic; S = total degree; see ``search_objective``).  The best code over the restarts wins; ties keep the
-    earlier restart.
+    draws a position g = draw mod (n*b) and a fresh symbol.  Hill-climb
+    (walk = 0): the change is kept when the objective (U, F, L, D, S) does
+    not get worse (lexicographic; S = total degree; see
+    ``search_objective``), and the restart's result is its final code.
+    Plateau walk (walk = 1): the change is kept when (U, F) does not get
+    worse (U smaller, or U equal and F not larger), and the restart's result
+    is the best code it visited by the whole objective (the first one, on
+    ties).  The best result over the restarts wins; ties keep the earlier
+    restart.
     """
     kb = k * b
     if not (1 <= sigma <= kb) or kb > 64:
@@ -386,18 +391,27 @@ def array_search(n: int, k: int, b: int, sigma: int, seed: int,
             return (U, F, L, D, sum(len(s) for s in sy))
 
         cur = objective(syms)
+        run_best, run_syms = cur, list(syms)
         for _ in range(iters):
             g = rng.below(G)
             cand = _random_symbol(rng, kb, sigma)
             old = syms[g]
             syms[g] = cand
             obj = objective(syms)
-            if obj <= cur:
+            if walk:
+                keep = obj[0] < cur[0] or (obj[0] == cur[0] and obj[1] <= cur[1])
+            else:
+                keep = obj <= cur
+            if keep:
                 cur = obj
+                if walk and obj < run_best:
+                    run_best, run_syms = obj, list(syms)
             else:
                 syms[g] = old
-        if best_obj is None or cur < best_obj:
-            best_obj = cur
-            best = list(syms)
+        if not walk:
+            run_best, run_syms = cur, list(syms)
+        if best_obj is None or run_best < best_obj:
+            best_obj = run_best
+            best = run_syms
     cols = [[best[j * b + i] for i in range(b)] for j in range(n)]
     return Code("array", n=n, k=k, b=b, columns=cols)

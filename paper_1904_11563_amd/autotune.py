@@ -41,18 +41,36 @@ def index(prec: int, Mb: int, N: int, K: int) -> int:
     return ((prec * 8 + bucket(Mb)) * 8 + bucket(N)) * 8 + bucket(K)
 
 
-def load(path: str = TABLE_PATH) -> bool:
-    """Install the saved table in the library; False if there is none."""
+KERNEL_SOURCE = os.path.join(HERE, "csrc", "gemm_bf16.hip")
+
+
+def kernel_source_hash() -> str:
+    """Hash of the source holding the tuned kernels: a table measured on
+    other kernels is stale."""
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load(path: str = TABLE_PATH) -> str:
+    """Install the saved table in the library if it was measured on the
+    current kernels.  Returns what the grouped launch will use: "none" (no
+    table), "stale" (measured on other kernels; not installed), "default
+    won every bucket" (a current table with no override), or
+    "autotuned (n overrides)"."""
     from . import bpx
     if not os.path.exists(path):
-        return False
+        return "none"
     with open(path) as f:
         d = json.load(f)
+    if d.get("meta", {}).get("gemm_source") != kernel_source_hash():
+        return "stale"
     table = [-1] * N_ENTRIES
     for k, v in d["entries"].items():
         table[int(k)] = int(v)
     bpx.set_tile_table(table)
-    return True
+    n = len(d["entries"])
+    return f"autotuned ({n} overrides)" if n else "default won every bucket"
 
 
 def _gemm_phase_ms(bpx, torch, plans, As, Bs, Cs, ws, reps):
@@ -142,14 +160,15 @@ def main():
     args = ap.parse_args()
     t0 = time.time()
     c4 = bpx.Code.search(*[getattr(inputs.CODE_642, f) for f in
-                           ("n", "k", "b", "sigma", "seed", "restarts", "iters")])
+                           ("n", "k", "b", "sigma", "seed", "restarts", "iters", "walk")])
     c8 = bpx.Code.search(*[getattr(inputs.CODE_1282, f) for f in
-                           ("n", "k", "b", "sigma", "seed", "restarts", "iters")])
+                           ("n", "k", "b", "sigma", "seed", "restarts", "iters", "walk")])
     shapes = inputs.batch_shapes(0, args.count)
     entries, ms = tune_grouped(args.prec, shapes, {4: c4, 8: c8}, reps=args.reps)
     save(entries, {"prec": args.prec, "workload": "batch", "count": args.count,
                    "criterion": "grouped GEMM phase of the whole batch",
-                   "grouped_gemm_ms": round(ms, 4), "seconds": round(time.time() - t0, 1)})
+                   "grouped_gemm_ms": round(ms, 4), "seconds": round(time.time() - t0, 1),
+                   "gemm_source": kernel_source_hash()})
     print(f"saved {len(entries)} bucket overrides to {TABLE_PATH}", flush=True)
 
 

@@ -58,7 +58,8 @@ EXPORTS = [
 class CodeParams(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n", C.c_int32), ("k", C.c_int32), ("b", C.c_int32),
                 ("sigma_max", C.c_int32), ("restarts", C.c_int32), ("iters", C.c_int32),
-                ("mojette_qe", C.c_int32), ("seed", C.c_uint64)]
+                ("mojette_qe", C.c_int32), ("seed", C.c_uint64), ("walk", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 _p = C.c_void_p
@@ -143,8 +144,9 @@ class Code:
         self._h = handle if isinstance(handle, _p) else _p(handle)
 
     @classmethod
-    def build(cls, kind, n=0, k=0, b=0, sigma_max=0, restarts=1, iters=0, mojette_qe=0, seed=0):
-        prm = CodeParams(kind, n, k, b, sigma_max, restarts, iters, mojette_qe, seed)
+    def build(cls, kind, n=0, k=0, b=0, sigma_max=0, restarts=1, iters=0, mojette_qe=0, seed=0,
+              walk=0):
+        prm = CodeParams(kind, n, k, b, sigma_max, restarts, iters, mojette_qe, seed, walk, 0)
         h = _p()
         _check(_lib.bpx_code_build(C.byref(prm), C.byref(h)))
         return cls(h)
@@ -166,9 +168,9 @@ class Code:
         return cls.build(CODE_MOJETTE, n=n, k=k, b=b, mojette_qe=qe)
 
     @classmethod
-    def search(cls, n, k, b, sigma_max, seed, restarts, iters):
+    def search(cls, n, k, b, sigma_max, seed, restarts, iters, walk=0):
         return cls.build(CODE_ARRAY_SEARCH, n=n, k=k, b=b, sigma_max=sigma_max,
-                         restarts=restarts, iters=iters, seed=seed)
+                         restarts=restarts, iters=iters, seed=seed, walk=walk)
 
     @classmethod
     def from_columns(cls, n, k, b, columns):

@@ -203,11 +203,17 @@ uint64_t mask_of(const Sym& s) {
   return m;
 }
 
+// walk = 0: hill-climb, a change is kept when the whole objective does not
+// get worse.  walk = 1: plateau walk, a change is kept when (U, F) does not
+// get worse, so the search moves freely among codes with as few failing
+// subsets (the finer terms would otherwise pin it to the first local
+// optimum); the best code seen by the whole objective is kept.
 int array_search(int32_t n, int32_t k, int32_t b, int32_t sigma, uint64_t seed, int32_t restarts,
-                 int32_t iters, bpx_code* out, std::string* err) {
+                 int32_t iters, int32_t walk, bpx_code* out, std::string* err) {
   const int32_t kb = k * b;
-  if (kb > 64 || sigma < 1 || sigma > kb || restarts < 1 || iters < 0 || k > n) {
-    *err = "array search needs k <= n, k*b <= 64, 1 <= sigma <= k*b, restarts >= 1";
+  if (kb > 64 || sigma < 1 || sigma > kb || restarts < 1 || iters < 0 || k > n || walk < 0 ||
+      walk > 1) {
+    *err = "array search needs k <= n, k*b <= 64, 1 <= sigma <= k*b, restarts >= 1, walk 0 or 1";
     return BPX_E_INVALID;
   }
   const uint64_t full = kb == 64 ? ~0ull : ((1ull << kb) - 1);
@@ -226,6 +232,8 @@ int array_search(int32_t n, int32_t k, int32_t b, int32_t sigma, uint64_t seed, 
       degs[g] = (int32_t)syms[g].size();
     }
     Objective cur = evaluate(masks, degs, n, k, b, full);
+    Objective run_best = cur;
+    std::vector<Sym> run_syms = syms;
     Sym cand;
     for (int32_t it = 0; it < iters; ++it) {
       const int32_t g = (int32_t)rng.below((uint64_t)G);
@@ -235,17 +243,26 @@ int array_search(int32_t n, int32_t k, int32_t b, int32_t sigma, uint64_t seed, 
       masks[g] = mask_of(cand);
       degs[g] = (int32_t)cand.size();
       const Objective o = evaluate(masks, degs, n, k, b, full);
-      if (o <= cur) {
+      const bool keep = walk ? (o.U < cur.U || (o.U == cur.U && o.F <= cur.F)) : o <= cur;
+      if (keep) {
         cur = o;
         syms[g] = cand;
+        if (walk && o < run_best) {
+          run_best = o;
+          run_syms = syms;
+        }
       } else {
         masks[g] = old_m;
         degs[g] = old_d;
       }
     }
-    if (!have || cur < best_obj) {
-      best_obj = cur;
-      best = syms;
+    if (!walk) {
+      run_best = cur;
+      run_syms = syms;
+    }
+    if (!have || run_best < best_obj) {
+      best_obj = run_best;
+      best = run_syms;
       have = true;
     }
   }
@@ -259,6 +276,10 @@ int array_search(int32_t n, int32_t k, int32_t b, int32_t sigma, uint64_t seed, 
 }  // namespace
 
 int build_code(const bpx_code_params& p, bpx_code* out, std::string* err) {
+  if (p.reserved != 0) {
+    *err = "reserved field of the code parameters must be 0";
+    return BPX_E_INVALID;
+  }
   switch (p.kind) {
     case BPX_CODE_TABLE1:
       table1(out);
@@ -285,7 +306,8 @@ int build_code(const bpx_code_params& p, bpx_code* out, std::string* err) {
         *err = "array search needs n, k, b >= 1";
         return BPX_E_INVALID;
       }
-      return array_search(p.n, p.k, p.b, p.sigma_max, p.seed, p.restarts, p.iters, out, err);
+      return array_search(p.n, p.k, p.b, p.sigma_max, p.seed, p.restarts, p.iters, p.walk, out,
+                          err);
     default:
       *err = "unknown code kind";
       return BPX_E_INVALID;

@@ -64,11 +64,14 @@ class CodeSpec:
     restarts: int = 1
     iters: int = 0
     qe: int = 0
+    walk: int = 0        # search acceptance: 0 hill-climb, 1 plateau walk
 
 
 # Array codes at the workloads' parameters (the paper prints no construction
 # for them; they come from the deterministic search).
-CODE_642 = CodeSpec("search", n=6, k=4, b=2, sigma=3, seed=0, restarts=4, iters=2000)
+# (6,4,2): the plateau walk reaches one failing column pair, the fewest the
+# Bush bound allows at b = 2 (the hill-climb stops at two).
+CODE_642 = CodeSpec("search", n=6, k=4, b=2, sigma=4, seed=0, restarts=4, iters=4000, walk=1)
 CODE_1284 = CodeSpec("search", n=12, k=8, b=4, sigma=4, seed=0, restarts=1, iters=40000)
 CODE_1282 = CodeSpec("search", n=12, k=8, b=2, sigma=4, seed=0, restarts=1, iters=40000)
 CODE_MOJ = CodeSpec("mojette", n=24, k=16, b=8, qe=0)

@@ -25,10 +25,11 @@ def main(which):
             continue
         t = time.time()
         c = codes.array_search(spec.n, spec.k, spec.b, spec.sigma, spec.seed,
-                               spec.restarts, spec.iters)
+                               spec.restarts, spec.iters, walk=spec.walk)
         col_ptr, sym_ptr, sym_data = c.csr()
         out = {"n": spec.n, "k": spec.k, "b": spec.b, "sigma_max": spec.sigma,
                "seed": spec.seed, "restarts": spec.restarts, "iters": spec.iters,
+               "walk": spec.walk,
                "columns": [[list(s) for s in col] for col in c.columns],
                "col_ptr": col_ptr, "sym_ptr": sym_ptr, "sym_data": sym_data}
         path = os.path.join(HERE, f"search_{name}.json")

@@ -35,12 +35,12 @@ def fused_mode(mode):
 
 def _code642():
     s = inputs.CODE_642
-    return bpx.Code.search(s.n, s.k, s.b, s.sigma, s.seed, s.restarts, s.iters)
+    return bpx.Code.search(s.n, s.k, s.b, s.sigma, s.seed, s.restarts, s.iters, walk=s.walk)
 
 
 def _code1284():
     s = inputs.CODE_1284
-    return bpx.Code.search(s.n, s.k, s.b, s.sigma, s.seed, s.restarts, s.iters)
+    return bpx.Code.search(s.n, s.k, s.b, s.sigma, s.seed, s.restarts, s.iters, walk=s.walk)
 
 
 def _oracle(code):

@@ -40,7 +40,7 @@ def _say(*a):
 def lib_code(spec):
     if spec.kind == "search":
         return bpx.Code.search(spec.n, spec.k, spec.b, spec.sigma, spec.seed, spec.restarts,
-                               spec.iters)
+                               spec.iters, walk=spec.walk)
     if spec.kind == "mojette":
         return bpx.Code.mojette(spec.k, spec.b, spec.n, spec.qe)
     raise ValueError(spec.kind)

@@ -49,9 +49,10 @@ def test_search_small_budgets_match_oracle():
         seed = rng.next()
         restarts = 1 + rng.below(3)
         iters = rng.below(150)
-        got = bpx.Code.search(n, k, b, sig, seed, restarts, iters).columns()
-        want = codes.array_search(n, k, b, sig, seed, restarts, iters).columns
-        assert got == want, (n, k, b, sig, seed, restarts, iters)
+        for walk in (0, 1):
+            got = bpx.Code.search(n, k, b, sig, seed, restarts, iters, walk=walk).columns()
+            want = codes.array_search(n, k, b, sig, seed, restarts, iters, walk=walk).columns
+            assert got == want, (n, k, b, sig, seed, restarts, iters, walk)
 
 
 @pytest.mark.parametrize("name", ["642", "1282", "1284"])
@@ -61,7 +62,7 @@ def test_search_matches_golden_fixture(name):
         pytest.skip("fixture not generated")
     fx = json.load(open(path))
     c = bpx.Code.search(fx["n"], fx["k"], fx["b"], fx["sigma_max"], fx["seed"],
-                        fx["restarts"], fx["iters"])
+                        fx["restarts"], fx["iters"], walk=fx.get("walk", 0))
     col_ptr, sym_ptr, sym_data = c.csr()
     assert col_ptr.tolist() == fx["col_ptr"]
     assert sym_ptr.tolist() == fx["sym_ptr"]
@@ -254,7 +255,7 @@ def test_peel_slots_are_reused():
     exactly (the host execution in _compare)."""
     spec = inputs.CODE_642
     lib_code = bpx.Code.search(spec.n, spec.k, spec.b, spec.sigma, spec.seed, spec.restarts,
-                               spec.iters)
+                               spec.iters, walk=spec.walk)
     ocode = _oracle_code_from_lib(lib_code)
     fewer = 0
     for seed in range(8):

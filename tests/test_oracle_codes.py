@@ -329,3 +329,13 @@ def test_search_642_not_column_mds():
     c = codes.array_search(6, 4, 2, 3, seed=0, restarts=2, iters=300)
     U, F, _, _ = _brute_objective(c)
     assert U >= 1 and F == 0
+
+
+def test_search_642_workload_code_reaches_the_bush_optimum():
+    # The (6,4,2) code of the workloads (plateau walk) leaves exactly one
+    # failing 4-column subset, which the Bush-bound argument above shows is
+    # the fewest possible; recounted by the set-based peeler.
+    from paper_1904_11563_amd.inputs import CODE_642 as s
+    c = codes.array_search(s.n, s.k, s.b, s.sigma, s.seed, s.restarts, s.iters, walk=s.walk)
+    U, F, _, _ = _brute_objective(c)
+    assert U == 1 and F == 0

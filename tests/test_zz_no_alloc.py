@@ -24,7 +24,7 @@ def _say(*a):
 
 def _code642():
     s = inputs.CODE_642
-    return bpx.Code.search(s.n, s.k, s.b, s.sigma, s.seed, s.restarts, s.iters)
+    return bpx.Code.search(s.n, s.k, s.b, s.sigma, s.seed, s.restarts, s.iters, walk=s.walk)
 
 
 def _pair(plan, A, B):
