@@ -71,7 +71,7 @@ class CodeSpec:
 # for them; they come from the deterministic search).
 # (6,4,2): the plateau walk reaches one failing column pair, the fewest the
 # Bush bound allows at b = 2 (the hill-climb stops at two).
-CODE_642 = CodeSpec("search", n=6, k=4, b=2, sigma=4, seed=0, restarts=4, iters=4000, walk=1)
+CODE_642 = CodeSpec("search", n=6, k=4, b=2, sigma=3, seed=0, restarts=8, iters=6000, walk=1)
 CODE_1284 = CodeSpec("search", n=12, k=8, b=4, sigma=4, seed=0, restarts=1, iters=40000)
 CODE_1282 = CodeSpec("search", n=12, k=8, b=2, sigma=4, seed=0, restarts=1, iters=40000)
 CODE_MOJ = CodeSpec("mojette", n=24, k=16, b=8, qe=0)
