@@ -62,23 +62,24 @@ GEMM_SOURCE = {"f32": "gemm_f32.hip", "bf16": "gemm_bf16.hip", "bf16x3": "gemm_b
                "fp8": "gemm_fp8.hip", "fp8x2": "gemm_fp8.hip"}
 
 
-def kernel_source_hash(prec):
-    """Hash of the source file that holds the precision's GEMM kernels."""
+def source_hash(name):
+    """Hash of one kernel source file under the package's csrc/."""
     h = hashlib.sha256()
-    h.update(open(os.path.join(ROOT, "paper_1904_11563_amd", "csrc", GEMM_SOURCE[prec]),
-                  "rb").read())
+    h.update(open(os.path.join(ROOT, "paper_1904_11563_amd", "csrc", name), "rb").read())
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload, prec):
+def load_traffic(workload, prec, source):
     """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 counter summary, or None if missing or taken on other sources."""
+    rocprofv3 counter summary, or None if missing, taken on another kernel
+    source, or taken on another form of the step (source = the file that
+    holds the kernel the roofline names)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
         e = json.load(open(path))[f"{workload}:{prec}"]
-        if e.get("gemm_source") != kernel_source_hash(prec):
+        if e.get("gemm_source_file") != source or e.get("gemm_source") != source_hash(source):
             return None
         return e["bytes_per_launch"]
     except Exception:
@@ -312,9 +313,10 @@ def run_single(args):
     kernel = {"f32": f32_kernel, "bf16": bf16_kernel, "bf16x3": bf16_kernel,
               "fp8": "quant_b + quant_a + coded_gemm_fp8_wide_kernel, one call",
               "fp8x2": "quant_b + quant_a + coded_gemm_fp8_wide_kernel, one call"}[prec_name]
+    source = "gemm2d.hip" if two_d else "fused.hip" if fused else GEMM_SOURCE[prec_name]
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK[prec_name],
                 "unit": "TFLOP/s", "frac": achieved / PEAK[prec_name],
-                "traffic": load_traffic(w.name, prec_name), "kernel": kernel,
+                "traffic": load_traffic(w.name, prec_name, source), "kernel": kernel,
                 "flops_per_launch": gemm_flops, "launch_ms": gemm_ms}
     cfg = {"workload": w.name, "M": w.M, "K": w.K, "N": w.N,
            "code": f"{spec.kind}(n={spec.n},k={spec.k},b={spec.b})",
@@ -572,7 +574,7 @@ def run_batch(args):
                              "peel": phase_ms[2]},
                 "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[prec_name],
                              "unit": "TFLOP/s", "frac": achieved / PEAK[prec_name],
-                             "traffic": load_traffic("batch", prec_name),
+                             "traffic": load_traffic("batch", prec_name, "gemm_bf16.hip"),
                              "kernel": "gemm_bf16_flat_grouped_kernel (GEMM phase)",
                              "flops_per_launch": comp_flops, "launch_ms": phase_ms[1]},
                 "hbm": hbm})
