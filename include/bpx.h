@@ -382,7 +382,8 @@ bpx_status bpx_coded_matmul_grouped(bpx_plan* const* plans, const float* const* 
  * x = Mb, N, K) and the precision to a tile-shape index, indexed
  * ((prec*8 + bMb)*8 + bN)*8 + bK (8*8*8*5 entries; NULL clears it; entries
  * < 0 fall back to the default shape).  bpx_force_tile forces one shape for
- * every call (for the autotuner); -1 returns to the table.
+ * every call (for the autotuner and tests), which also keeps every call on
+ * the two-launch form; -1 returns to the table.
  * BF16 / BF16x3 shapes 0-3 are 128x128, 64x128, 128x256 and 64x256 tiles of
  * one symbol; 4 (the default) is 128x256 tiles over the stacked rows of all
  * computed symbols, used when K is a multiple of 32 (otherwise shape 1).

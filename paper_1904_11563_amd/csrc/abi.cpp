@@ -277,7 +277,9 @@ bpx_status scratch_address(void** out) {
 // with eight symbols is 2^27).
 bool fused_params(bpx_plan* plan, const float* A, int64_t lda, const float* B, int64_t ldb,
                   float* C, int64_t ldc, FusedParams* f) {
-  if (g_fused_mode == 0 || plan->grid != 1 || plan->fused_steps.empty()) return false;
+  // a forced GEMM tile shape names the two-launch form's tiling
+  if (g_fused_mode == 0 || g_force_tile >= 0 || plan->grid != 1 || plan->fused_steps.empty())
+    return false;
   const double macs = (double)plan->computed.size() * (double)plan->Mb * (double)plan->K *
                       (double)plan->N;
   if (g_fused_mode == 1 && macs > 2147483648.0) return false;
