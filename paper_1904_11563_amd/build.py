@@ -86,8 +86,20 @@ def build(verbose: bool = False) -> str:
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stderr}")
+    check_launch_stubs(tmp)
     os.replace(tmp, LIB)
     return LIB
+
+
+def check_launch_stubs(lib):
+    """Fail if a kernel's host-side launch stub is referenced but undefined.
+    The compiler's host pass can drop a kernel template's stub without a
+    diagnostic (seen with a lambda that hands a builtin captured array
+    elements), and the link still succeeds; the launch would then fail."""
+    r = subprocess.run(["nm", "-u", lib], capture_output=True, text=True)
+    missing = [l.split()[-1] for l in r.stdout.splitlines() if "__device_stub__" in l]
+    if missing:
+        raise RuntimeError("kernels without a launch stub: " + ", ".join(missing))
 
 
 def build_sanitized() -> str:
@@ -117,6 +129,7 @@ def build_sanitized() -> str:
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stderr}")
+    check_launch_stubs(SAN_LIB)
     return SAN_LIB
 
 
