@@ -427,6 +427,37 @@ def test_padding_blocks_without_rows():
         assert np.array_equal(C.astype(np.float64), A.astype(np.float64) @ B)
 
 
+@pytest.mark.parametrize("prec", [bpx.PREC_F32, bpx.PREC_BF16, bpx.PREC_BF16X3])
+def test_smallest_products_exact(prec):
+    """The degenerate end of the method: a single output row (M = 1, so one
+    data block holds the row and every other block is empty), K = 4 (the
+    smallest K the device path takes) and N = 1 and 5, through both forms,
+    on every decodable two-column arrival of Table I and on the (6,4,2)
+    code; integer operands, so each result is exact."""
+    cases = [(bpx.Code.table1(), 5, 3), (code642(), 6, 2)]
+    for code, n, lost in cases:
+        for N in (1, 5):
+            A = inputs.integers(40 + N, inputs.TAG_A, (1, 4))
+            B = inputs.integers(40 + N, inputs.TAG_B, (4, N))
+            R = A.astype(np.float64) @ B.astype(np.float64)
+            n_ok = 0
+            for kept in itertools.combinations(range(n), n - lost):
+                order = list(kept) + [j for j in range(n) if j not in kept]
+                plan = bpx.Plan(code, order, lost, bpx.MODE_ERASURE, 1, 4, N, prec)
+                if not plan.decodable:
+                    continue
+                for mode in (0, 2):     # two-launch form, fused form
+                    bpx.set_fused_peel(mode)
+                    try:
+                        _say("smallest product", n, N, kept, "prec", prec, "fused", mode)
+                        C = run(plan, A, B)
+                    finally:
+                        bpx.set_fused_peel(1)
+                    assert np.array_equal(C.astype(np.float64), R), (n, N, kept, mode)
+                n_ok += 1
+            assert n_ok >= 1
+
+
 def test_argument_errors():
     code = bpx.Code.table1()
     plan = bpx.Plan(code, [0, 1, 2, 3, 4], 0, bpx.MODE_STRAGGLER, 16, 6, 8)

@@ -289,6 +289,23 @@ def test_plan_rejects_bad_arrival():
         bpx.Plan(c, [0, 1, 2, 3, 4], 6, bpx.MODE_ERASURE, 4, 4, 4)
 
 
+def test_plan_rejects_empty_shapes_and_unknown_precision():
+    # An empty product (any of M, K, N zero or negative) and an unknown
+    # precision are argument errors, reported before any device work.
+    c = bpx.Code.table1()
+    order = [0, 1, 2, 3, 4]
+    for M, K, N in ((0, 4, 4), (4, 0, 4), (4, 4, 0), (-1, 4, 4)):
+        with pytest.raises(bpx.BpxError) as e:
+            bpx.Plan(c, order, 0, bpx.MODE_STRAGGLER, M, K, N)
+        assert e.value.status == bpx.E_INVALID, (M, K, N)
+    with pytest.raises(bpx.BpxError) as e:
+        bpx.Plan(c, order, 0, bpx.MODE_STRAGGLER, 4, 4, 4, 99)
+    assert e.value.status == bpx.E_INVALID
+    # the smallest product the method has: one row, one column, one k
+    tiny = bpx.Plan(c, order, 0, bpx.MODE_STRAGGLER, 1, 1, 1)
+    assert tiny.decodable and tiny.info()["Mb"] == 1
+
+
 def test_workspace_bytes():
     c = bpx.Code.table3()
     plan = bpx.Plan(c, [3, 4, 0, 1, 2], 0, bpx.MODE_FULL, 90, 16, 10)
