@@ -65,27 +65,47 @@ __device__ __forceinline__ float block_amax(float m, float* red) {
 
 // grid: (Kp/128, Mbp/128, n_sym), 256 threads; thread t owns float4 chunks
 // f = t + 256 i (i < 16): row f / 32, k offset (f % 32) * 4 of the tile.
+// Members are summed one at a time, ascending, each member's 16 loads
+// issued together: the member's rows of the tile are a raw buffer whose
+// range ends at its last row that exists (rows past Mb or M read zero),
+// and chunks past K are sent out of range.
+__device__ __forceinline__ v4f qload(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
+  return __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, 0, 0));
+}
 __global__ __launch_bounds__(256) void quant_a_kernel(Fp8Params p) {
   __shared__ float red[4];
   const int kb = blockIdx.x, rb = blockIdx.y, si = blockIdx.z;
-  const int id_off = p.syms[4 * si + 0];
-  const int deg = p.syms[4 * si + 1];
+  const int id_off = __builtin_amdgcn_readfirstlane(p.syms[4 * si + 0]);
+  const int deg = __builtin_amdgcn_readfirstlane(p.syms[4 * si + 1]);
   const int32_t* ids = p.ids + id_off;
   const int64_t k0 = (int64_t)kb * 128, r0 = (int64_t)rb * 128;
-  v4f x[16];
-  float amax = 0.f;
+  uint32_t off[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     const int f = threadIdx.x + 256 * i;
-    const int64_t r = r0 + f / 32, k = k0 + (f % 32) * 4;
-    v4f s = {0.f, 0.f, 0.f, 0.f};
-    if (r < p.Mb && k < p.K) {
-      for (int m = 0; m < deg; ++m) {
-        const int64_t row = (int64_t)ids[m] * p.Mb + r;
-        if (row < p.M) s += *reinterpret_cast<const v4f*>(p.A + row * p.lda + k);
-      }
-    }
-    x[i] = s;
+    const int64_t lr = f / 32, kk = (f % 32) * 4;
+    off[i] = k0 + kk < p.K ? (uint32_t)((lr * p.lda + kk) * 4) : 0x80000000u;
+  }
+  v4f x[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) x[i] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int m = 0; m < deg; ++m) {
+    const int64_t first = (int64_t)__builtin_amdgcn_readfirstlane(ids[m]) * p.Mb + r0;
+    int64_t rows = p.Mb - r0 < p.M - first ? p.Mb - r0 : p.M - first;
+    rows = rows < 0 ? 0 : (rows > 128 ? 128 : rows);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(p.A + first * p.lda + k0), (short)0, (int)(rows * p.lda * 4),
+        0x00020000);
+    v4f v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = qload(rs, off[i]);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) x[i] += v[i];
+  }
+  float amax = 0.f;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const v4f s = x[i];
     amax = fmaxf(amax, fmaxf(fmaxf(fabsf(s[0]), fabsf(s[1])), fmaxf(fabsf(s[2]), fabsf(s[3]))));
   }
   amax = block_amax(amax, red);
@@ -539,6 +559,8 @@ __global__ __launch_bounds__(wide8::NT, 1) void coded_gemm_fp8_wide_kernel(Fp8Pa
 
 hipError_t launch_quant_a(const Fp8Params& p, hipStream_t stream) {
   if (p.n_sym == 0) return hipSuccess;
+  // a member's 128-row tile is one buffer of 32-bit byte offsets
+  if (128 * p.lda * 4 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(p.Kp / 128), (unsigned)(p.Mbp / 128), (unsigned)p.n_sym);
   hipLaunchKernelGGL(quant_a_kernel, grid, dim3(256), 0, stream, p);
   return hipGetLastError();
