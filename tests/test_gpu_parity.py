@@ -688,6 +688,39 @@ def test_bf16_flat_tile_exact_and_identical_to_per_symbol_tile(prec):
     assert np.array_equal(Cf4, Cf1)
 
 
+@pytest.mark.parametrize("prec", [bpx.PREC_BF16, bpx.PREC_BF16X3])
+def test_bf16_flat_tile_k_tails_and_degrees(prec):
+    """The flat tiling's k loop for every stage count from 1 to 7 (its
+    two-stage body and each tail after it) and for tiles whose largest
+    symbol degree runs from 1 to 4: the (12,8,4) code in FULL mode (all 48
+    symbols, degrees 1 to 4), Mb = 64, so a 128-row tile holds two symbols.
+    Integer operands decode exactly; float operands give the per-symbol
+    tiling's bits."""
+    s = inputs.CODE_1284
+    code = bpx.Code.search(s.n, s.k, s.b, s.sigma, s.seed, s.restarts, s.iters, walk=s.walk)
+    M, N = 32 * 64 - 37, 260
+    for nk in range(1, 8):
+        K = 32 * nk
+        plan = bpx.Plan(code, list(range(12)), 0, bpx.MODE_FULL, M, K, N, prec)
+        assert plan.decodable
+        A = inputs.integers(40 + nk, inputs.TAG_A, (M, K))
+        B = inputs.integers(40 + nk, inputs.TAG_B, (K, N))
+        Af = inputs.normal(40 + nk, inputs.TAG_A, (M, K))
+        Bf = inputs.normal(40 + nk, inputs.TAG_B, (K, N))
+        _say("flat k tail", "prec", prec, "K", K)
+        try:
+            bpx.force_tile(4)
+            C = run(plan, A, B)
+            assert np.array_equal(C.astype(np.float64),
+                                  A.astype(np.float64) @ B.astype(np.float64)), K
+            Cf4 = run(plan, Af, Bf)
+            bpx.force_tile(1)
+            Cf1 = run(plan, Af, Bf)
+        finally:
+            bpx.force_tile(-1)
+        assert np.array_equal(Cf4, Cf1), K
+
+
 def test_grouped_flat_tile_exact_and_identical_to_per_symbol_tile():
     """The grouped launch with every product on the flat-row tiling: integer
     operands bit exact, float operands bit-identical to the per-symbol
