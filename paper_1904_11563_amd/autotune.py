@@ -42,6 +42,10 @@ def index(prec: int, Mb: int, N: int, K: int) -> int:
 
 
 KERNEL_SOURCE = os.path.join(HERE, "csrc", "gemm_bf16.hip")
+# The library's BF16 / BF16x3 shape where the table has no entry (the flat
+# 128 x 256 tiling, tile 4 of bpx_tile_count): an entry naming it would be
+# no override at all.
+DEFAULT_TILE = 4
 
 
 def kernel_source_hash() -> str:
@@ -124,19 +128,26 @@ def tune_grouped(prec_name: str, shapes, codes_by_k, reps: int = 5, seed: int = 
     chosen = {}
     for key in sorted(work, key=lambda x: -work[x]):
         cur = table[key]
+        # the bucket's current choice is timed again in the same round as
+        # the candidates, so that a slow drift of the clock is no win
+        bpx.set_tile_table(table)
+        ref = _gemm_phase_ms(bpx, torch, plans, As, Bs, Cs, ws, reps)
         times = {}
         for t in range(n_tiles):
+            if t == DEFAULT_TILE:
+                continue  # the default is what the reference run used
             table[key] = t
             bpx.set_tile_table(table)
             times[t] = _gemm_phase_ms(bpx, torch, plans, As, Bs, Cs, ws, reps)
         t_best = min(times, key=times.get)
-        if times[t_best] < best * 0.99:
+        if times[t_best] < ref * 0.99:
             table[key] = t_best
             best = times[t_best]
         else:
             table[key] = cur
+            best = ref
         chosen[key] = table[key]
-        log(f"bucket {key} ({work[key] / 1e9:.1f} GFLOP): " +
+        log(f"bucket {key} ({work[key] / 1e9:.1f} GFLOP): default={ref:.3f} " +
             " ".join(f"t{t}={x:.3f}" for t, x in times.items()) +
             f" -> {'t%d' % table[key] if table[key] >= 0 else 'default'} (total {best:.3f} ms)")
     bpx.set_tile_table(table)
