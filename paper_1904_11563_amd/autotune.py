@@ -80,6 +80,15 @@ def load(path: str = TABLE_PATH) -> str:
     return f"autotuned ({n} overrides)" if n else "default won every bucket"
 
 
+def accept(ref_ms: float, best_ms: float, share: float) -> bool:
+    """Keep a bucket's best candidate over the default (timed in the same
+    round, ref_ms) only if it wins by more than 1 % and by no more than 1.5
+    times the bucket's share of the work: a bucket cannot save more than its
+    own time, so a larger "gain" is run-to-run noise (1-2 % on this phase)."""
+    gain = ref_ms - best_ms
+    return gain > 0.01 * ref_ms and gain <= 1.5 * share * ref_ms
+
+
 def _gemm_phase_ms(bpx, torch, plans, As, Bs, Cs, ws, reps):
     """Shortest of `reps` timings of the grouped GEMM phase (group built with
     the table currently installed)."""
@@ -144,11 +153,7 @@ def tune_grouped(prec_name: str, shapes, codes_by_k, reps: int = 5, seed: int = 
             bpx.set_tile_table(table)
             times[t] = _gemm_phase_ms(bpx, torch, plans, As, Bs, Cs, ws, reps)
         t_best = min(times, key=times.get)
-        # A bucket's tiles can save at most about its share of the phase; a
-        # larger "gain" is run-to-run noise (1-2 % on this phase), and so is
-        # one under 1 %.
-        gain = ref - times[t_best]
-        if gain > 0.01 * ref and gain <= 1.5 * work[key] / total * ref:
+        if accept(ref, times[t_best], work[key] / total):
             table[key] = t_best
             best = times[t_best]
         else:

@@ -28,3 +28,14 @@ def test_load_labels_and_staleness(tmp_path):
 
 def test_default_tile_is_a_compiled_shape():
     assert 0 <= autotune.DEFAULT_TILE < bpx.tile_count(bpx.PREC_BF16X3)
+
+
+def test_accept_rule():
+    # a real win within the bucket's share is kept
+    assert autotune.accept(4.70, 4.50, 0.10)
+    # under 1 %: noise
+    assert not autotune.accept(4.70, 4.66, 0.50)
+    # larger than the bucket could save (1.5 x its 0.1 % share): noise
+    assert not autotune.accept(4.70, 4.60, 0.001)
+    # a loss is never kept
+    assert not autotune.accept(4.70, 4.80, 0.50)
