@@ -578,14 +578,17 @@ int32_t fp8_tile_count() { return 2; }
 constexpr int32_t kFp8GroupM = 4;
 
 // tile 0: 128 x 128 per symbol; tile 1: 128 x 256 tiles over all symbols'
-// codes (used when Np is a multiple of 256, otherwise tile 0).
+// codes (used when Np is a multiple of 256, otherwise tile 0).  The wide
+// kernel addresses each chunk from a 64-bit base (the tile's first row),
+// so only a lane's offset inside one tile (128 rows of A codes, 256 rows of
+// B codes: under 256 Kp bytes) has to fit the buffer instruction's 32
+// bits; the code matrices themselves may pass 4 GiB.
 hipError_t launch_coded_gemm_fp8(const Fp8Params& p0, int32_t tile, hipStream_t stream) {
   Fp8Params p = p0;
   if (p.n_sym == 0) return hipSuccess;
   const int64_t R = (int64_t)p.n_sym * p.Mbp;
   const int64_t bm = 128;
-  if (tile == 1 && p.Np % 256 == 0 && R % bm == 0 && R * p.Kp < (int64_t)1 << 32 &&
-      p.Np * p.Kp < (int64_t)1 << 32) {
+  if (tile == 1 && p.Np % 256 == 0 && R % bm == 0 && 256 * p.Kp < (int64_t)1 << 31) {
     p.tiles_m = (int32_t)(R / bm);
     if (p.group_m <= 0) p.group_m = kFp8GroupM;
     p.tiles_n = (int32_t)(p.Np / 256);

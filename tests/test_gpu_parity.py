@@ -978,6 +978,38 @@ def test_fp8_mojette_full_size_sampled():
     assert np.isfinite(C).all()
 
 
+def test_fp8_wide_tile_past_4gib_of_codes():
+    """Mojette Construction A (k=16, n=24, b=8) in FULL mode at M = K =
+    16384: 2112 coded blocks of 128 rows, so each FP8 code plane is 2112 x
+    128 x 16384 bytes, past 2^32.  The wide 128x256 kernel (addressing each
+    tile from a 64-bit base) must agree with the per-symbol 128x128 tile
+    (1e-6: same codes, the MFMA's own summation order) and with float64 on
+    two sampled rows of every block (3e-2)."""
+    code = bpx.Code.mojette(16, 8, 24, 0)
+    M, K, N = 16384, 16384, 256
+    A = inputs.normal(24, inputs.TAG_A, (M, K))
+    B = inputs.normal(24, inputs.TAG_B, (K, N))
+    plan = bpx.Plan(code, list(range(24)), 0, bpx.MODE_FULL, M, K, N, bpx.PREC_FP8X2)
+    inf = plan.info()
+    _say("fp8 FULL plan", inf)
+    assert inf["decodable"] and inf["Mb"] == 128
+    assert inf["n_computed"] * 128 * K > 2 ** 32
+    C_wide = run(plan, A, B)
+    try:
+        bpx.force_tile(0)
+        C_sym = run(plan, A, B)
+    finally:
+        bpx.force_tile(-1)
+    d = relf(C_wide, C_sym)
+    rows = np.concatenate([[s * 128 + 5, s * 128 + 99] for s in range(128)])
+    R = A[rows].astype(np.float64) @ B.astype(np.float64)
+    e = relf(C_wide[rows], R)
+    _say("fp8 FULL wide vs per-symbol", d, "sampled relF", e)
+    assert np.isfinite(C_wide).all()
+    assert d <= 1e-6
+    assert e <= TOL_FP8
+
+
 def test_fp8_integer_operands_small_chain():
     # Table III depth-9 chain through the FP8x2 path: the relative error
     # stays at the FP8 level (no blow-up through the subtraction chain).
