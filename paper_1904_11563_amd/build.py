@@ -30,24 +30,29 @@ EXTRA = {"gemm_f32.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
          "gemm2d.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"]}
 
 
-# Host-sanitizer build (CPU tests only): the integer host core (code
+# Host-sanitizer builds (CPU tests only): the integer host core (code
 # construction, planning, the C ABI) built with AddressSanitizer and
-# UndefinedBehaviorSanitizer on its host pass; device code is unchanged.
+# UndefinedBehaviorSanitizer, or with ThreadSanitizer, on its host pass;
+# device code is unchanged.
 HOST_CORE = ("code.cpp", "plan.cpp", "abi.cpp")
-SAN_FLAGS = "-Xarch_host -fsanitize=address -Xarch_host -fsanitize=undefined".split()
-SAN_LIB = os.path.join(BUILD, "san", "libbpx_san.so")
+SAN_KINDS = {
+    "address": ("-Xarch_host -fsanitize=address -Xarch_host -fsanitize=undefined".split(),
+                ["-shared-libasan"], "libbpx_san.so", "libclang_rt.asan-x86_64.so"),
+    "thread": (["-Xarch_host", "-fsanitize=thread"], [], "libbpx_tsan.so",
+               "libclang_rt.tsan-x86_64.so"),
+}
 
 
-def sanitizer_runtime():
-    """Path of the compiler's shared AddressSanitizer runtime (to preload)."""
-    r = subprocess.run([HIPCC, "-print-file-name=libclang_rt.asan-x86_64.so"],
-                       capture_output=True, text=True)
+def sanitizer_runtime(kind: str = "address"):
+    """Path of the compiler's shared sanitizer runtime (to preload)."""
+    rt = SAN_KINDS[kind][3]
+    r = subprocess.run([HIPCC, "-print-file-name=" + rt], capture_output=True, text=True)
     path = r.stdout.strip()
     if not os.path.isabs(path):
         base = os.path.join(os.path.dirname(os.path.realpath(HIPCC)), "..", "llvm", "lib",
                             "clang")
         for v in sorted(os.listdir(base)) if os.path.isdir(base) else []:
-            cand = os.path.join(base, v, "lib", "linux", "libclang_rt.asan-x86_64.so")
+            cand = os.path.join(base, v, "lib", "linux", rt)
             if os.path.exists(cand):
                 path = cand
     return path
@@ -102,21 +107,24 @@ def check_launch_stubs(lib):
         raise RuntimeError("kernels without a launch stub: " + ", ".join(missing))
 
 
-def build_sanitized() -> str:
-    """libbpx_san.so: the host core with ASan + UBSan, linked with the
-    regular device objects (built first if missing)."""
+def build_sanitized(kind: str = "address") -> str:
+    """libbpx_san.so (kind "address": ASan + UBSan) or libbpx_tsan.so (kind
+    "thread": TSan): the host core instrumented, linked with the regular
+    device objects (built first if missing)."""
+    flags, link_extra, lib_name, _ = SAN_KINDS[kind]
     if not all(os.path.exists(os.path.join(BUILD, os.path.basename(f) + ".o"))
                for f in sources()):
         build()
-    out_dir = os.path.dirname(SAN_LIB)
+    out_dir = os.path.join(BUILD, "san")
     os.makedirs(out_dir, exist_ok=True)
+    out_lib = os.path.join(out_dir, lib_name)
     objs = []
     for src in sources():
         name = os.path.basename(src)
         if name in HOST_CORE:
-            obj = os.path.join(out_dir, name + ".o")
+            obj = os.path.join(out_dir, f"{kind}.{name}.o")
             cmd = [HIPCC, "-O1", "-g", "-fPIC", "-std=c++17", "--offload-arch=gfx950",
-                   "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"] + SAN_FLAGS + \
+                   "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"] + flags + \
                   ["-x", "hip", "-c", src, "-o", obj]
             r = subprocess.run(cmd, capture_output=True, text=True)
             if r.returncode != 0:
@@ -124,17 +132,19 @@ def build_sanitized() -> str:
             objs.append(obj)
         else:
             objs.append(os.path.join(BUILD, name + ".o"))
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950"] + SAN_FLAGS + \
-        ["-shared-libasan", "-o", SAN_LIB] + objs
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950"] + flags + link_extra + \
+        ["-o", out_lib] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stderr}")
-    check_launch_stubs(SAN_LIB)
-    return SAN_LIB
+    check_launch_stubs(out_lib)
+    return out_lib
 
 
 if __name__ == "__main__":
-    if "--sanitize" in sys.argv:
+    if "--sanitize-thread" in sys.argv:
+        print(build_sanitized("thread"))
+    elif "--sanitize" in sys.argv:
         print(build_sanitized())
     else:
         print(build(verbose=True))
