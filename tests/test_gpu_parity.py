@@ -1147,6 +1147,99 @@ def test_grouped_graph_replay_matches_eager():
         del junk
 
 
+@pytest.mark.parametrize("prec", [bpx.PREC_F32, bpx.PREC_BF16X3, bpx.PREC_FP8X2])
+def test_single_product_graph_replay_matches_eager(prec):
+    """One product through the two-launch path captured in a HIP graph, as
+    the benchmark times it: the (12,8,4) code, Mb = 256, a shifted-
+    exponential arrival (36 coded products, a peel of depth up to 12); FP32
+    takes the 256x256 tiles with the short grid split along K and reduced,
+    BF16x3 the B split and flat tiles, FP8x2 the B and A quantisation and
+    the wide FP8 tiles.  Three replays with eager work in between each
+    equal the eager result bit for bit."""
+    s_ = inputs.CODE_1284
+    code = bpx.Code.search(s_.n, s_.k, s_.b, s_.sigma, s_.seed, s_.restarts, s_.iters,
+                           walk=s_.walk)
+    perm, _ = inputs.shifted_exp_arrival(0, 12)
+    M, K, N = 8192, 1024, 1024
+    plan = bpx.Plan(code, list(perm), 0, bpx.MODE_STRAGGLER, M, K, N, prec)
+    assert plan.decodable
+    plan.upload()
+    A = torch.from_numpy(inputs.normal(9, inputs.TAG_A, (M, K))).cuda()
+    B = torch.from_numpy(inputs.normal(9, inputs.TAG_B, (K, N))).cuda()
+    ws = bpx.alloc_workspace(plan)
+    C_eager = torch.empty((M, N), device="cuda")
+    bpx.coded_matmul(plan, A, B, C_eager, ws)
+    torch.cuda.synchronize()
+    C = torch.empty((M, N), device="cuda")
+    graph = torch.cuda.CUDAGraph()
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        with torch.cuda.graph(graph, stream=st):
+            bpx.coded_matmul(plan, A, B, C, ws)
+    torch.cuda.current_stream().wait_stream(st)
+    torch.cuda.synchronize()
+    _say("graph replay", prec, plan.info())
+    for rep in range(3):
+        C.fill_(float("nan"))
+        ws.fill_(0xA5)                          # the workspace is rewritten by every replay
+        junk = torch.randn(512, 512, device="cuda") @ torch.randn(512, 512, device="cuda")
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(C, C_eager), rep
+        del junk
+
+
+def test_distinct_plans_from_two_threads_on_two_streams():
+    """Distinct plan handles used from two host threads at once, each on its
+    own stream (default priority): the (6,4,2) code in FP32 (two columns
+    erased) and the (12,8,4) code in BF16x3 (straggler prefix), five calls
+    each, every result equal to the same call made alone beforehand.  The first call of each thread also uploads its
+    plan's tables (under the library's lock)."""
+    import threading
+    s_ = inputs.CODE_1284
+    c1284 = bpx.Code.search(s_.n, s_.k, s_.b, s_.sigma, s_.seed, s_.restarts, s_.iters,
+                            walk=s_.walk)
+    jobs = []
+    arr642, lost642 = inputs.erasure_arrival(40, 6, 2)
+    arr1284, _ = inputs.shifted_exp_arrival(41, 12)
+    for i, (code, perm, lost, mode, prec, M, K, N) in enumerate(
+            [(code642(), arr642, lost642, bpx.MODE_ERASURE, bpx.PREC_F32, 1024, 512, 768),
+             (c1284, arr1284, 0, bpx.MODE_STRAGGLER, bpx.PREC_BF16X3, 2048, 512, 512)]):
+        ref_plan = bpx.Plan(code, list(perm), lost, mode, M, K, N, prec)
+        assert ref_plan.decodable
+        A = torch.from_numpy(inputs.normal(40 + i, inputs.TAG_A, (M, K))).cuda()
+        B = torch.from_numpy(inputs.normal(40 + i, inputs.TAG_B, (K, N))).cuda()
+        want = torch.empty((M, N), device="cuda")
+        bpx.coded_matmul(ref_plan, A, B, want, bpx.alloc_workspace(ref_plan))
+        torch.cuda.synchronize()
+        plan = bpx.Plan(code, list(perm), lost, mode, M, K, N, prec)
+        jobs.append((plan, A, B, want, bpx.alloc_workspace(plan),
+                     torch.empty((M, N), device="cuda"), torch.cuda.Stream()))
+    errors = []
+
+    def body(plan, A, B, want, ws, C, stream):
+        try:
+            with torch.cuda.stream(stream):
+                for _ in range(5):
+                    C.fill_(float("nan"))
+                    bpx.coded_matmul(plan, A, B, C, ws, stream=stream)
+                    stream.synchronize()
+                    if not torch.equal(C, want):
+                        errors.append("result differs")
+        except Exception as e:
+            errors.append(repr(e))
+
+    ts = [threading.Thread(target=body, args=j) for j in jobs]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    torch.cuda.synchronize()
+    assert not errors, errors
+
+
 def test_grouped_peel_split_mixed_programs_exact():
     """The grouped peel's workgroup ranges are cut by program cost: a group
     mixing products with no peel steps (identity code, every block its own
