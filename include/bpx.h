@@ -71,7 +71,7 @@ typedef enum {
   BPX_PREC_F32 = 0,    /* FP32 operands, FP32 MFMA                            */
   BPX_PREC_BF16 = 1,   /* operands rounded to BF16 (RNE), one MFMA pass       */
   BPX_PREC_BF16X3 = 2, /* split BF16: hi.hi + hi.lo + lo.hi, FP32 accumulate  */
-  BPX_PREC_FP8 = 3,    /* e4m3 with one FP32 scale per 128x128 block          */
+  BPX_PREC_FP8 = 3,    /* e4m3, one power-of-two scale per 128x128 block      */
   BPX_PREC_FP8X2 = 4   /* coded operand split into two e4m3 terms, B one term */
 } bpx_prec;
 
@@ -246,12 +246,13 @@ bpx_status bpx_plan_workspace_bytes(const bpx_plan* plan, size_t* ws_bytes,
  *            up to 32, zero past K)
  *   FP8*:    [0] Y, [1] Aq, [2] Aq2, [3] sA, [4] Bq, [5] sB: e4m3 codes of
  *            the coded blocks ([n_computed][Mbp][Kp] bytes), of the FP8x2
- *            residual term, their FP32 scales ([n_computed][Mbp/128][Kp/128]),
- *            the codes of B transposed ([Np][Kp]) and its scales
+ *            residual term, their scales as FP32 values ([n_computed][Mbp/128]
+ *            [Kp/128]), the codes of B transposed ([Np][Kp]) and its scales
  *            ([Kp/128][Np/128]); Mbp, Kp, Np = Mb, K, N rounded up to 128.
- * Per 128 x 128 block: s = amax / 448 (1 if amax = 0), code =
- * e4m3(clamp(x / s, +-448)) with round to nearest even; the FP8x2 residual
- * code is e4m3(clamp((x / s - code) * 16, +-448)). */
+ * Per 128 x 128 block: s = the smallest power of two with amax <= 448 s (1 if
+ * amax = 0, at least 2^-122), code = e4m3(clamp(x / s, +-448)) with round to
+ * nearest even; the FP8x2 residual code is e4m3(clamp((x / s - code) * 16,
+ * +-448)).  The GEMM applies s through the MFMA's E8M0 scale operands. */
 bpx_status bpx_plan_workspace_layout(const bpx_plan* plan, size_t* offsets, int32_t n);
 
 /* Upload the plan's device tables now (hipMalloc + synchronous copy on the

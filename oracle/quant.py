@@ -10,10 +10,12 @@ bits, no infinities, the all-ones pattern is NaN): normal values
 values m 2^-9.  Rounding is to nearest, ties to even, and values beyond
 448 saturate to +-448.
 
-Per 128 x 128 block of a matrix: s = amax / 448 (1 if amax = 0), codes of
-x / s.  Where a float decides a code, the computation is done in float32 in
-the same order as the device (x / s is one float32 division), so the codes
-must agree bit for bit.
+Per 128 x 128 block of a matrix: s = the smallest power of two with
+amax <= 448 s (1 if amax = 0; at least 2^-122, so that the FP8x2 residual's
+s / 16 is still a normal power of two), codes of x / s.  The paper fixes no
+low-precision format; a power-of-two block scale is what the matrix unit's
+own E8M0 scale operands represent exactly.  Dividing by a power of two is
+exact, so x / s (float32) and every code agree bit for bit with the device.
 """
 from __future__ import annotations
 
@@ -61,12 +63,27 @@ def e4m3_decode(code):
     return s * val
 
 
+MIN_SCALE_EXP = -122
+
+
+def block_scale(amax) -> np.float32:
+    """The smallest power of two s with amax <= 448 s, at least 2^-122;
+    1 for amax = 0.  Stepped up from a start known to be at or below it."""
+    amax = float(amax)
+    if amax == 0.0:
+        return np.float32(1.0)
+    e = max(MIN_SCALE_EXP, int(np.floor(np.log2(amax / E4M3_MAX))) - 2)
+    while E4M3_MAX * 2.0 ** e < amax:
+        e += 1
+    return np.float32(2.0 ** e)
+
+
 def quantize_block(x, residual: bool = False):
     """Scale and codes of one float32 block; with residual, also the codes of
     (x/s - q) * 16.  Returns (scale, codes[, residual codes])."""
     x = np.asarray(x, dtype=np.float32)
     amax = np.float32(np.max(np.abs(x))) if x.size else np.float32(0)
-    s = np.float32(amax / np.float32(E4M3_MAX)) if amax > 0 else np.float32(1.0)
+    s = block_scale(amax)
     v = (x / s).astype(np.float32)
     c = e4m3_code(np.clip(v, -E4M3_MAX, E4M3_MAX))
     if not residual:

@@ -1,19 +1,22 @@
-// FP8-e4m3 coded products with one FP32 scale per 128 x 128 block.
+// FP8-e4m3 coded products with one power-of-two scale per 128 x 128 block.
 //
 // quant_a_kernel  - the encode for FP8: per computed symbol g and 128 x 128
 //                   tile of its coded block C_g = sum of its data blocks A_s
 //                   (Sec. II, XOR read as a real sum), sum the members in
-//                   FP32 (ascending), take the tile's amax, scale
-//                   s = amax / 448 (s = 1 when amax = 0) and store
+//                   FP32 (ascending), take the tile's amax, scale s = the
+//                   smallest power of two with amax <= 448 s (1 when
+//                   amax = 0, at least 2^-122) and store
 //                   q = e4m3(clamp(x / s, +-448)) (round to nearest even).
 //                   FP8x2 also stores the residual term
 //                   q2 = e4m3(clamp((x / s - q) * 16, +-448)), so that
-//                   x ~ s (q + q2 / 16).
+//                   x ~ s (q + q2 / 16).  x / s is exact.
 // quant_b_kernel  - the same for B, written transposed (N x Kp, k
 //                   contiguous) so that both MFMA operands read k runs.
-// coded_gemm_fp8  - Y_g = sum over 128-wide k chunks of sA sB (qA . qB), the
-//                   chunk product on v_mfma_scale_f32_16x16x128_f8f6f4 with
-//                   unit E8M0 scales, the FP32 scaling applied per chunk.
+// coded_gemm_fp8  - Y_g = sum over 128-wide k chunks of sA sB (qA . qB) on
+//                   v_mfma_scale_f32_16x16x128_f8f6f4, whose E8M0 scale
+//                   operands carry sA and sB (and the residual plane's
+//                   extra 2^-4), so that every chunk accumulates straight
+//                   into the MFMA accumulators with no vector arithmetic.
 //
 // The encode cannot be folded into the GEMM prologue here: a tile's scale
 // needs the amax of the whole 128 x 128 coded tile, and every N-tile of the
@@ -36,6 +39,24 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef int v8i __attribute__((ext_vector_type(8)));
 
 constexpr float kE4M3Max = 448.f;
+
+// The smallest power of two s with amax <= 448 s, at least 2^-122 (so that
+// s / 16 is a normal power of two too); 1 for amax = 0.  With amax =
+// (1 + f 2^-23) 2^(b - 127): 448 = 1.75 2^8, so s = 2^(b - 135) when
+// f <= 0.75 2^23, else 2^(b - 134).  Exact integer work, no rounding.
+constexpr int kMinScaleExp = -122;
+__device__ __forceinline__ float pow2_scale(float amax) {
+  if (!(amax > 0.f)) return 1.f;
+  const unsigned bits = __float_as_uint(amax);
+  const int b = (int)((bits >> 23) & 0xffu);
+  int e = b - ((bits & 0x7fffffu) <= 0x600000u ? 135 : 134);
+  e = e < kMinScaleExp ? kMinScaleExp : e;
+  return __uint_as_float((unsigned)(e + 127) << 23);
+}
+// Scales are read through the constant address space (scalar loads).
+typedef __attribute__((address_space(4))) float cfloat;
+// E8M0 byte of a power-of-two scale: its biased exponent.
+__device__ __forceinline__ int e8m0(float s) { return (int)((__float_as_uint(s) >> 23) & 0xffu); }
 
 __device__ __forceinline__ float clamp448(float v) {
   return v > kE4M3Max ? kE4M3Max : (v < -kE4M3Max ? -kE4M3Max : v);
@@ -109,7 +130,7 @@ __global__ __launch_bounds__(256) void quant_a_kernel(Fp8Params p) {
     amax = fmaxf(amax, fmaxf(fmaxf(fabsf(s[0]), fabsf(s[1])), fmaxf(fabsf(s[2]), fabsf(s[3]))));
   }
   amax = block_amax(amax, red);
-  const float sc = amax > 0.f ? amax / kE4M3Max : 1.f;
+  const float sc = pow2_scale(amax);
   const int64_t sym_bytes = p.Mbp * p.Kp;
   unsigned char* q = p.aq + (int64_t)si * sym_bytes;
   unsigned char* q2 = p.aq2 ? p.aq2 + (int64_t)si * sym_bytes : nullptr;
@@ -153,7 +174,7 @@ __global__ __launch_bounds__(256) void quant_b_kernel(Fp8Params p) {
     amax = fmaxf(amax, fmaxf(fmaxf(fabsf(s[0]), fabsf(s[1])), fmaxf(fabsf(s[2]), fabsf(s[3]))));
   }
   amax = block_amax(amax, red);
-  const float sc = amax > 0.f ? amax / kE4M3Max : 1.f;
+  const float sc = pow2_scale(amax);
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     const int f = threadIdx.x + 256 * i;
@@ -241,8 +262,8 @@ __global__ __launch_bounds__(kThreads, 1) void coded_gemm_fp8_kernel(Fp8Params p
   const unsigned char* Aq = p.aq + (int64_t)si * sym_bytes + (int64_t)m0 * p.Kp;
   const unsigned char* Aq2 = X2 ? p.aq2 + (int64_t)si * sym_bytes + (int64_t)m0 * p.Kp : nullptr;
   const unsigned char* Bq = p.bq + (int64_t)n0 * p.Kp;
-  const float* sa = p.sa + ((int64_t)si * (p.Mbp / 128) + mt) * (p.Kp / 128);
-  const float* sb = p.sb + nt;
+  const cfloat* sa = (const cfloat*)p.sa + ((int64_t)si * (p.Mbp / 128) + mt) * (p.Kp / 128);
+  const cfloat* sb = (const cfloat*)p.sb + nt;
   const int64_t np128 = p.Np / 128;
 
   // 16-byte pieces: row f / 8, byte offset (f % 8) * 16; 4 per thread per plane
@@ -294,20 +315,18 @@ __global__ __launch_bounds__(kThreads, 1) void coded_gemm_fp8_kernel(Fp8Params p
 #pragma unroll
     for (int j = 0; j < FN; ++j)  // output column wn TN + 4 c16 + j, at row 16 j + c16
       b[j] = frag(st + (NA * BM + wn * TN + 16 * j + c16) * CK, x0);
-    const float s = sa[c] * sb[(int64_t)c * np128];
+    // the chunk's scales as E8M0 bytes (uniform: scalar loads)
+    const int ea = __builtin_amdgcn_readfirstlane(e8m0(sa[c]));
+    const int eb = __builtin_amdgcn_readfirstlane(e8m0(sb[(int64_t)c * np128]));
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
-        v4f part = {0.f, 0.f, 0.f, 0.f};
-        if (X2) {
-          part = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[1][i], b[j], part, 0, 0, 0,
-                                                                   127, 0, 127);
-          part *= 0.0625f;  // the residual term carries a factor 16
-        }
-        part = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[0][i], b[j], part, 0, 0, 0,
-                                                                 127, 0, 127);
-        acc[i][j] += s * part;
+        if (X2)  // the residual plane carries a factor 16: scale 2^-4 more
+          acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[1][i], b[j], acc[i][j], 0,
+                                                                        0, 0, ea - 4, 0, eb);
+        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[0][i], b[j], acc[i][j], 0,
+                                                                      0, 0, ea, 0, eb);
       }
     if (more) store((c + 1) & 1);
     __syncthreads();
@@ -352,11 +371,11 @@ __global__ __launch_bounds__(kThreads, 1) void coded_gemm_fp8_kernel(Fp8Params p
 // GEMM whose 128-row blocks each belong to one symbol.  Tiles of BM x 256
 // (BM = 128: a 256-row tile with FP32 accumulators does not fit the
 // registers), 8 waves of (BM / WM) x (256 / WN), each wave inside one 128 x 128
-// scale block, so the per-chunk scale sA sB is one number per wave.  The
-// residual plane's factor 1/16 is applied by the MFMA's own E8M0 scale
-// (2^-4), so both planes accumulate into the same chunk product before the
-// FP32 scale is applied.  Global loads are raw buffer loads (scalar
-// resource per plane and chunk, one 32-bit per-thread offset).
+// scale block, so a chunk's scales sA and sB are one E8M0 byte each per
+// wave; the MFMA applies them (and the residual plane's extra 2^-4) exactly
+// and both planes accumulate straight into the accumulators.  Global loads
+// are raw buffer loads (scalar resource per plane and chunk, one 32-bit
+// per-thread offset).
 namespace wide8 {
 constexpr int BN = 256;
 constexpr int NT = 512;
@@ -450,14 +469,20 @@ __global__ __launch_bounds__(wide8::NT, 1) void coded_gemm_fp8_wide_kernel(Fp8Pa
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
+  // The chunk scales are read as constant memory at wave-uniform addresses,
+  // i.e. by scalar loads: a vector load of them at the top of a chunk would
+  // make its wait (vmcnt) also wait for the next chunk's copies to LDS.
   const int64_t kc128 = Kp / 128;
-  const float* sa = p.sa + ((m0 + wm * TM) / 128) * kc128;
-  const float* sbp = p.sb + (n0 + wn * TN) / 128;
   const int64_t np128 = p.Np / 128;
+  const int rba = __builtin_amdgcn_readfirstlane((int)((m0 + wm * TM) / 128));
+  const int cbb = __builtin_amdgcn_readfirstlane((int)((n0 + wn * TN) / 128));
+  const cfloat* sa = (const cfloat*)p.sa + (int64_t)rba * kc128;
+  const cfloat* sbp = (const cfloat*)p.sb + cbb;
 
   const int x0 = lds_off(c16, 2 * q) - c16 * CK;  // fragment rows are c16 mod 16
   auto compute = [&](const unsigned char* st, int c) __attribute__((always_inline)) {
-    const float s = sa[c] * sbp[(int64_t)c * np128];
+    const int ea = __builtin_amdgcn_readfirstlane(e8m0(sa[c]));
+    const int eb = __builtin_amdgcn_readfirstlane(e8m0(sbp[(int64_t)c * np128]));
     v8i a[NA][FM];
 #pragma unroll
     for (int i = 0; i < FM; ++i)
@@ -470,25 +495,20 @@ __global__ __launch_bounds__(wide8::NT, 1) void coded_gemm_fp8_wide_kernel(Fp8Pa
       for (int jj = 0; jj < 4; ++jj)  // output column jg 64 + 4 c16 + jj, at row 16 jj + c16
         b[jj] = frag(st + (NA * BM + wn * TN + jg * 64 + 16 * jj + c16) * CK, x0);
       // Per fragment row: the four residual-plane products first, then the
-      // four main-plane products accumulating onto them, so that no MFMA
-      // waits on the one just issued (same sums in the same order).
+      // four main-plane products, so that no MFMA waits on the one just
+      // issued; per output the same MFMAs in the same order as the
+      // per-symbol tile.
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
-        v4f part[4];
+        if (X2)  // residual plane: scale 2^-4 more
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-          part[jj] = v4f{0.f, 0.f, 0.f, 0.f};
-          if (X2)  // residual plane, E8M0 scale 2^-4
-            part[jj] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[NA - 1][i], b[jj],
-                                                                         part[jj], 0, 0, 0, 123, 0,
-                                                                         127);
-        }
+          for (int jj = 0; jj < 4; ++jj)
+            acc[i][jg * 4 + jj] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                a[NA - 1][i], b[jj], acc[i][jg * 4 + jj], 0, 0, 0, ea - 4, 0, eb);
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj)
-          part[jj] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[0][i], b[jj], part[jj], 0,
-                                                                       0, 0, 127, 0, 127);
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) acc[i][jg * 4 + jj] += s * part[jj];
+          acc[i][jg * 4 + jj] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+              a[0][i], b[jj], acc[i][jg * 4 + jj], 0, 0, 0, ea, 0, eb);
       }
     }
   };

@@ -39,10 +39,27 @@ def test_round_to_nearest_even_and_saturation():
     assert np.max(np.abs(quant.e4m3_value(x) - x) / x) <= 2.0 ** -4
 
 
+def test_block_scale_is_the_smallest_sufficient_power_of_two():
+    # worked cases: 448 fits 448 * 2^0; the next float32 above it needs 2^1;
+    # 224 = 448 / 2 fits 2^-1; 1 needs 2^-8 (448 * 2^-9 = 0.875 < 1)
+    assert quant.block_scale(np.float32(448.0)) == 1.0
+    assert quant.block_scale(np.nextafter(np.float32(448.0), np.float32(1e9))) == 2.0
+    assert quant.block_scale(np.float32(224.0)) == 0.5
+    assert quant.block_scale(np.float32(1.0)) == 2.0 ** -8
+    assert quant.block_scale(np.float32(0.0)) == 1.0
+    assert quant.block_scale(np.float32(1e-40)) == np.float32(2.0 ** -122)   # the floor
+    rng = np.random.default_rng(2)
+    for amax in np.exp(rng.uniform(-60, 60, 2000)).astype(np.float32):
+        s = float(quant.block_scale(amax))
+        m, _ = np.frexp(s)
+        assert m == 0.5                                  # a power of two
+        assert amax <= 448 * s and amax > 448 * s / 2    # and the smallest one
+
+
 def test_block_scaling():
     x = np.random.default_rng(1).standard_normal((128, 128)).astype(np.float32)
     s, c = quant.quantize_block(x)
-    assert s == np.float32(np.max(np.abs(x)) / np.float32(448))
+    assert s == quant.block_scale(np.max(np.abs(x)))
     assert quant.e4m3_decode(c).max() <= 448
     err = np.linalg.norm(quant.e4m3_decode(c) * s - x) / np.linalg.norm(x)
     assert err < 0.05
