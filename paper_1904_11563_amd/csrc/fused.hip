@@ -19,11 +19,12 @@
 //
 // Layout of a workgroup (8 waves): the B column strip B[0:K, n0:n0+BN] is
 // staged in LDS once (FP32: row-major k x BN; BF16: transposed per column,
-// k contiguous, split into hi / lo planes); wave w then computes the
-// computed symbols w, w+8, ... over all of K with no barrier, loading the
-// members' A rows straight from global memory (float4 per lane) and summing
-// them in FP32 registers; releasers' tiles are stored to LDS; after one
-// barrier every thread peels its own elements.
+// k contiguous, split into hi / lo planes); the tile's 16 rows of every
+// data block pass through LDS one k group at a time (double-buffered, the
+// next groups' loads in flight), and wave w computes the computed symbols
+// w, w+8, ... from them, summing each symbol's members in FP32 registers
+// (BF16: then splitting the sum into hi / lo); releasers' tiles are stored
+// to LDS; after one barrier every thread peels its own elements.
 //
 // MFMA fragments: FP32 v_mfma_f32_16x16x4_f32 with lane (q, c) supplying
 // A row c, k = 4q + t of each 16-wide chunk for MFMA t, and subtile j's
@@ -35,6 +36,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -45,6 +47,7 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef float v2f __attribute__((ext_vector_type(2)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
 typedef unsigned short us;
 
 constexpr int kThreads = 512;  // 8 waves: two per SIMD, so one wave's waits hide behind the other
@@ -394,23 +397,37 @@ __global__ __launch_bounds__(kThreads) void fused_f32_kernel(FusedParams p) {
       for (int t = 0; t < 4; ++t)
         b[t] = *reinterpret_cast<const vb*>(Bs + (grp * KG + 16 * c + 4 * q + t) * LDB +
                                             JN * c16);
+      // Symbol j's chunk with its degree D known at compile time (a scalar
+      // branch on the wave-uniform degree): the D granule reads issue
+      // together and the members are summed in ascending order, unmasked.
+      auto chunk = [&](int j, auto deg) __attribute__((always_inline)) {
+        constexpr int D = decltype(deg)::value;
+        v4f gr[D];
 #pragma unroll
-      for (int j = 0; j < kMS; ++j) {
-        if (j >= ws.n) break;
-        // all kMaxDeg granules are read unconditionally (a member past the
-        // degree reads block 0 and is masked), so the reads issue together
-        v4f gr[kMaxDeg];
-#pragma unroll
-        for (int m = 0; m < kMaxDeg; ++m) gr[m] = a_granule<KG>(As, ws.id[j][m], h, c16, g);
+        for (int m = 0; m < D; ++m) gr[m] = a_granule<KG>(As, ws.id[j][m], h, c16, g);
         v4f a = gr[0];
 #pragma unroll
-        for (int m = 1; m < kMaxDeg; ++m) a += m < ws.deg[j] ? gr[m] : v4f{0.f, 0.f, 0.f, 0.f};
+        for (int m = 1; m < D; ++m) a += gr[m];
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
           for (int jj = 0; jj < JN; ++jj)
             acc[j][jj] =
                 __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], lane_of(b[t], jj), acc[j][jj], 0, 0, 0);
+      };
+#pragma unroll
+      for (int j = 0; j < kMS; ++j) {
+        if (j >= ws.n) break;
+        const int d = ws.deg[j];
+        if (d == 1)
+          chunk(j, std::integral_constant<int, 1>{});
+        else if (d == 2)
+          chunk(j, std::integral_constant<int, 2>{});
+        else if (d == 3)
+          chunk(j, std::integral_constant<int, 3>{});
+        else if (d == kMaxDeg)
+          chunk(j, std::integral_constant<int, kMaxDeg>{});
+        // (a symbol with no members adds nothing: its product stays zero)
       }
     }
   };
@@ -429,14 +446,29 @@ __global__ __launch_bounds__(kThreads) void fused_f32_kernel(FusedParams p) {
 }
 
 // ------------------------------------------------------- BF16 / BF16x3 --
+// hi = bf16(x) and lo = bf16(x - hi), both round to nearest even, converted
+// two values at a time (one v_cvt_pk_bf16_f32 per pair; the same roundings
+// as converting each value alone).
+__device__ __forceinline__ void split2(float x, float y, __bf16* h, __bf16* l) {
+  const v2f p = {x, y};
+  const v2bf hp = __builtin_convertvector(p, v2bf);
+  const v2bf lp = __builtin_convertvector(p - __builtin_convertvector(hp, v2f), v2bf);
+  h[0] = hp[0];
+  h[1] = hp[1];
+  l[0] = lp[0];
+  l[1] = lp[1];
+}
 __device__ __forceinline__ void split8(v4f x0, v4f x1, v8bf* hi, v8bf* lo) {
+  __bf16 h[8], l[8];
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const __bf16 h0 = (__bf16)x0[e], h1 = (__bf16)x1[e];
-    (*hi)[e] = h0;
-    (*hi)[4 + e] = h1;
-    (*lo)[e] = (__bf16)(x0[e] - (float)h0);
-    (*lo)[4 + e] = (__bf16)(x1[e] - (float)h1);
+  for (int e = 0; e < 4; e += 2) {
+    split2(x0[e], x0[e + 1], h + e, l + e);
+    split2(x1[e], x1[e + 1], h + 4 + e, l + 4 + e);
+  }
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    (*hi)[e] = h[e];
+    (*lo)[e] = l[e];
   }
 }
 
@@ -497,12 +529,8 @@ __global__ __launch_bounds__(kThreads) void fused_bf16_kernel(FusedParams p) {
         if (f >= items) continue;
         const int col = f % BN, k0 = (f / BN) * 8;
         v8bf hi, lo;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const __bf16 h = (__bf16)v[u][e];
-          hi[e] = h;
-          lo[e] = (__bf16)(v[u][e] - (float)h);
-        }
+        split8(v4f{v[u][0], v[u][1], v[u][2], v[u][3]}, v4f{v[u][4], v[u][5], v[u][6], v[u][7]},
+               &hi, &lo);
         *reinterpret_cast<v8bf*>(Bh + (size_t)col * KS + k0) = hi;
         if (X3) *reinterpret_cast<v8bf*>(Bl + (size_t)col * KS + k0) = lo;
       }
@@ -532,21 +560,24 @@ __global__ __launch_bounds__(kThreads) void fused_bf16_kernel(FusedParams p) {
         bh[jj] = *reinterpret_cast<const v8bf*>(Bh + off);
         if (X3) bl[jj] = *reinterpret_cast<const v8bf*>(Bl + off);
       }
+      // Symbol j's chunk with its degree D known at compile time: the 2 D
+      // granule reads issue together, the members are summed in ascending
+      // order and nothing is masked.  The degree is wave-uniform, so the
+      // branch below is a scalar one; the chunk body is VALU work (sums and
+      // splits) next to three MFMAs, so every masked add saved counts.
+      auto chunk = [&](int j, auto deg) __attribute__((always_inline)) {
+        constexpr int D = decltype(deg)::value;
+        v4f g0[D], g1[D];
 #pragma unroll
-      for (int j = 0; j < kMS; ++j) {
-        if (j >= ws.n) break;
-        // unconditional reads, masked past the degree (see the FP32 kernel)
-        v4f g0[kMaxDeg], g1[kMaxDeg];
-#pragma unroll
-        for (int m = 0; m < kMaxDeg; ++m) {
+        for (int m = 0; m < D; ++m) {
           g0[m] = a_granule<KG>(As, ws.id[j][m], h, c16, 2 * q);
           g1[m] = a_granule<KG>(As, ws.id[j][m], h, c16, 2 * q + 1);
         }
         v4f a0 = g0[0], a1 = g1[0];
 #pragma unroll
-        for (int m = 1; m < kMaxDeg; ++m) {
-          a0 += m < ws.deg[j] ? g0[m] : v4f{0.f, 0.f, 0.f, 0.f};
-          a1 += m < ws.deg[j] ? g1[m] : v4f{0.f, 0.f, 0.f, 0.f};
+        for (int m = 1; m < D; ++m) {
+          a0 += g0[m];
+          a1 += g1[m];
         }
         v8bf ah, al;
         split8(a0, a1, &ah, &al);
@@ -558,6 +589,20 @@ __global__ __launch_bounds__(kThreads) void fused_bf16_kernel(FusedParams p) {
           }
           acc[j][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[jj], acc[j][jj], 0, 0, 0);
         }
+      };
+#pragma unroll
+      for (int j = 0; j < kMS; ++j) {
+        if (j >= ws.n) break;
+        const int d = ws.deg[j];
+        if (d == 1)
+          chunk(j, std::integral_constant<int, 1>{});
+        else if (d == 2)
+          chunk(j, std::integral_constant<int, 2>{});
+        else if (d == 3)
+          chunk(j, std::integral_constant<int, 3>{});
+        else if (d == kMaxDeg)
+          chunk(j, std::integral_constant<int, kMaxDeg>{});
+        // (a symbol with no members adds nothing: its product stays zero)
       }
     }
   };
