@@ -389,19 +389,21 @@ __global__ __launch_bounds__(kThreads) void fused_f32_kernel(FusedParams p) {
   const int stage = p.kb * AStage<KG>::kFloats;
   auto compute = [&](int grp) __attribute__((always_inline)) {
     const float* As = As0 + (grp & 1) * stage;
+    // Symbol j's whole k group with its degree D known at compile time (one
+    // scalar branch on the wave-uniform degree per group): the D granule
+    // reads of a chunk issue together, the next chunk's reads can go out
+    // under this chunk's MFMAs, and the members are summed in ascending
+    // order, unmasked.
+    auto group = [&](int j, auto deg) __attribute__((always_inline)) {
+      constexpr int D = decltype(deg)::value;
 #pragma unroll
-    for (int c = 0; c < KG / 16; ++c) {  // 16-wide k chunks
-      const int h = c >> 1, g = (c & 1) * 4 + q;
-      vb b[4];
+      for (int c = 0; c < KG / 16; ++c) {  // 16-wide k chunks
+        const int h = c >> 1, g = (c & 1) * 4 + q;
+        vb b[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-        b[t] = *reinterpret_cast<const vb*>(Bs + (grp * KG + 16 * c + 4 * q + t) * LDB +
-                                            JN * c16);
-      // Symbol j's chunk with its degree D known at compile time (a scalar
-      // branch on the wave-uniform degree): the D granule reads issue
-      // together and the members are summed in ascending order, unmasked.
-      auto chunk = [&](int j, auto deg) __attribute__((always_inline)) {
-        constexpr int D = decltype(deg)::value;
+        for (int t = 0; t < 4; ++t)
+          b[t] = *reinterpret_cast<const vb*>(Bs + (grp * KG + 16 * c + 4 * q + t) * LDB +
+                                              JN * c16);
         v4f gr[D];
 #pragma unroll
         for (int m = 0; m < D; ++m) gr[m] = a_granule<KG>(As, ws.id[j][m], h, c16, g);
@@ -414,21 +416,21 @@ __global__ __launch_bounds__(kThreads) void fused_f32_kernel(FusedParams p) {
           for (int jj = 0; jj < JN; ++jj)
             acc[j][jj] =
                 __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], lane_of(b[t], jj), acc[j][jj], 0, 0, 0);
-      };
-#pragma unroll
-      for (int j = 0; j < kMS; ++j) {
-        if (j >= ws.n) break;
-        const int d = ws.deg[j];
-        if (d == 1)
-          chunk(j, std::integral_constant<int, 1>{});
-        else if (d == 2)
-          chunk(j, std::integral_constant<int, 2>{});
-        else if (d == 3)
-          chunk(j, std::integral_constant<int, 3>{});
-        else if (d == kMaxDeg)
-          chunk(j, std::integral_constant<int, kMaxDeg>{});
-        // (a symbol with no members adds nothing: its product stays zero)
       }
+    };
+#pragma unroll
+    for (int j = 0; j < kMS; ++j) {
+      if (j >= ws.n) break;
+      const int d = ws.deg[j];
+      if (d == 1)
+        group(j, std::integral_constant<int, 1>{});
+      else if (d == 2)
+        group(j, std::integral_constant<int, 2>{});
+      else if (d == 3)
+        group(j, std::integral_constant<int, 3>{});
+      else if (d == kMaxDeg)
+        group(j, std::integral_constant<int, kMaxDeg>{});
+      // (a symbol with no members adds nothing: its product stays zero)
     }
   };
   pipeline(ng, stage, As0, ast, p, r1, r2, compute);
@@ -551,22 +553,20 @@ __global__ __launch_bounds__(kThreads) void fused_bf16_kernel(FusedParams p) {
   const int stage = p.kb * AStage<KG>::kFloats;
   auto compute = [&](int grp) __attribute__((always_inline)) {
     const float* As = As0 + (grp & 1) * stage;
+    // Symbol j's whole k group with its degree D known at compile time (see
+    // the FP32 kernel); the chunk body is VALU work (sums and splits) next
+    // to three MFMAs, so every masked add saved counts.
+    auto group = [&](int j, auto deg) __attribute__((always_inline)) {
+      constexpr int D = decltype(deg)::value;
 #pragma unroll
-    for (int h = 0; h < KG / 32; ++h) {  // 32-wide k chunks: lane takes k = 8q .. 8q+7
-      v8bf bh[JN], bl[JN];
+      for (int h = 0; h < KG / 32; ++h) {  // 32-wide k chunks: lane takes k = 8q .. 8q+7
+        v8bf bh[JN], bl[JN];
 #pragma unroll
-      for (int jj = 0; jj < JN; ++jj) {
-        const size_t off = (size_t)(16 * jj + c16) * KS + grp * KG + 32 * h + 8 * q;
-        bh[jj] = *reinterpret_cast<const v8bf*>(Bh + off);
-        if (X3) bl[jj] = *reinterpret_cast<const v8bf*>(Bl + off);
-      }
-      // Symbol j's chunk with its degree D known at compile time: the 2 D
-      // granule reads issue together, the members are summed in ascending
-      // order and nothing is masked.  The degree is wave-uniform, so the
-      // branch below is a scalar one; the chunk body is VALU work (sums and
-      // splits) next to three MFMAs, so every masked add saved counts.
-      auto chunk = [&](int j, auto deg) __attribute__((always_inline)) {
-        constexpr int D = decltype(deg)::value;
+        for (int jj = 0; jj < JN; ++jj) {
+          const size_t off = (size_t)(16 * jj + c16) * KS + grp * KG + 32 * h + 8 * q;
+          bh[jj] = *reinterpret_cast<const v8bf*>(Bh + off);
+          if (X3) bl[jj] = *reinterpret_cast<const v8bf*>(Bl + off);
+        }
         v4f g0[D], g1[D];
 #pragma unroll
         for (int m = 0; m < D; ++m) {
@@ -589,21 +589,21 @@ __global__ __launch_bounds__(kThreads) void fused_bf16_kernel(FusedParams p) {
           }
           acc[j][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[jj], acc[j][jj], 0, 0, 0);
         }
-      };
-#pragma unroll
-      for (int j = 0; j < kMS; ++j) {
-        if (j >= ws.n) break;
-        const int d = ws.deg[j];
-        if (d == 1)
-          chunk(j, std::integral_constant<int, 1>{});
-        else if (d == 2)
-          chunk(j, std::integral_constant<int, 2>{});
-        else if (d == 3)
-          chunk(j, std::integral_constant<int, 3>{});
-        else if (d == kMaxDeg)
-          chunk(j, std::integral_constant<int, kMaxDeg>{});
-        // (a symbol with no members adds nothing: its product stays zero)
       }
+    };
+#pragma unroll
+    for (int j = 0; j < kMS; ++j) {
+      if (j >= ws.n) break;
+      const int d = ws.deg[j];
+      if (d == 1)
+        group(j, std::integral_constant<int, 1>{});
+      else if (d == 2)
+        group(j, std::integral_constant<int, 2>{});
+      else if (d == 3)
+        group(j, std::integral_constant<int, 3>{});
+      else if (d == kMaxDeg)
+        group(j, std::integral_constant<int, kMaxDeg>{});
+      // (a symbol with no members adds nothing: its product stays zero)
     }
   };
   pipeline(ng, stage, As0, ast, p, r1, r2, compute);
