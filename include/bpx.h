@@ -217,12 +217,13 @@ bpx_status bpx_plan_schedule(const bpx_plan* plan, const int32_t** computed,
  * inspection and host-side checks).  steps: n_steps records of step_words
  * int32, in execution order: {s, src, nsub, sub_off, f64, slot, write, brow,
  * bcol}: data block s is Y[src] (src >= 0, a workspace Y slot) or the block
- * already in C (src = -1) minus the values held in the nsub LDS slots
+ * already in C (src = -1) minus the values held in the nsub slots
  * subs[sub_off ..], accumulated in FP64 (f64 = 1) or FP32 with
- * compensation; the result is kept in LDS slot `slot` (>= 0) for later
- * steps and written to C (write = 1); brow, bcol locate s in the block grid.
- * Slots are reused once their block's last subtraction has run; n_slots is
- * the number in use at most.  Sec. I-A's peeling, in the order of the
+ * compensation; the result is kept in slot `slot` (>= 0) for later steps
+ * and written to C (write = 1); brow, bcol locate s in the block grid.
+ * Slots are per-thread storage (registers for a single product whose
+ * program needs at most 12, else LDS), reused once their block's last
+ * subtraction has run; n_slots is the number in use at most.  Sec. I-A's peeling, in the order of the
  * release rounds.  Any pointer may be NULL. */
 bpx_status bpx_plan_peel_program(const bpx_plan* plan, const int32_t** steps, int32_t* n_steps,
                                  int32_t* step_words, const int32_t** subs, int32_t* n_subs,

@@ -5,7 +5,9 @@
 // schedule is identical for every element of the Mb x N block, so each
 // thread runs the whole program for its own element (row r, column c of
 // every block) with no barriers between release rounds.  Values that later
-// steps subtract are kept in this thread's LDS column.
+// steps subtract are kept in this thread's LDS column, or, for a single
+// product in the vector form whose program needs at most kRegSlots of
+// them, in registers.
 //
 // Accumulation: FP32 with Kahan compensation for depth <= 4; FP64 for
 // deeper releases; subtrahends in ascending id order.  Rows past M (padding
@@ -122,8 +124,54 @@ __device__ __forceinline__ v4f gload4(const float* ptr) {
 }
 __device__ __forceinline__ void gstore4(float* ptr, v4f v) { *(gv4f*)ptr = v; }
 
+// Where a thread keeps the values later steps subtract (slot s of this
+// thread's four columns): in LDS, one column of slots per thread ...
 template <int THREADS>
-__device__ __forceinline__ void peel_block4(const PeelParams& p, int64_t block, v4f* xs,
+struct LdsSlots {
+  v4f* xs;
+  __device__ __forceinline__ v4f get(int s) const { return xs[s * THREADS + threadIdx.x]; }
+  __device__ __forceinline__ void put(int s, v4f x) { xs[s * THREADS + threadIdx.x] = x; }
+};
+// ... or in registers, for programs with at most kRegSlots live slots:
+// slots 0-7 in a 32-float vector, 8-11 in a 16-float vector, reached
+// through the GPR index mode by the slot number, which every lane shares
+// (so the workgroup's LDS holds only the program, and the chip holds every
+// row of a large block at once instead of in LDS-limited rounds).
+typedef float v32f __attribute__((ext_vector_type(32)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+constexpr int kRegSlots = 12;
+struct RegSlots {
+  v32f a = {};
+  v16f b = {};
+  __device__ __forceinline__ v4f get(int s) const {
+    s = __builtin_amdgcn_readfirstlane(s);
+    if (s < 8) {
+      const int i = 4 * s;
+      return v4f{a[i], a[i + 1], a[i + 2], a[i + 3]};
+    }
+    const int i = 4 * (s - 8);
+    return v4f{b[i], b[i + 1], b[i + 2], b[i + 3]};
+  }
+  __device__ __forceinline__ void put(int s, v4f x) {
+    s = __builtin_amdgcn_readfirstlane(s);
+    if (s < 8) {
+      const int i = 4 * s;
+      a[i] = x[0];
+      a[i + 1] = x[1];
+      a[i + 2] = x[2];
+      a[i + 3] = x[3];
+    } else {
+      const int i = 4 * (s - 8);
+      b[i] = x[0];
+      b[i + 1] = x[1];
+      b[i + 2] = x[2];
+      b[i + 3] = x[3];
+    }
+  }
+};
+
+template <int THREADS, int KB, typename Slots>
+__device__ __forceinline__ void peel_block4(const PeelParams& p, int64_t block, Slots& xs,
                                             const PeelStep* steps, const int32_t* subs) {
   const int tid = threadIdx.x;
   const int64_t n4 = p.N / 4;
@@ -134,10 +182,10 @@ __device__ __forceinline__ void peel_block4(const PeelParams& p, int64_t block, 
   const int64_t c = active ? (e - r * n4) * 4 : 0;
   const int64_t slot_elems = p.Mb * p.N;
 
-  for (int st0 = 0; st0 < p.nsteps; st0 += kBatch) {
-    v4f y[kBatch];
+  for (int st0 = 0; st0 < p.nsteps; st0 += KB) {
+    v4f y[KB];
 #pragma unroll
-    for (int i = 0; i < kBatch; ++i) {
+    for (int i = 0; i < KB; ++i) {
       y[i] = v4f{0.f, 0.f, 0.f, 0.f};
       const int st = st0 + i;
       if (st < p.nsteps && active) {
@@ -152,7 +200,7 @@ __device__ __forceinline__ void peel_block4(const PeelParams& p, int64_t block, 
       }
     }
 #pragma unroll
-    for (int i = 0; i < kBatch; ++i) {
+    for (int i = 0; i < KB; ++i) {
       const int st = st0 + i;
       if (st >= p.nsteps) break;
       const PeelStep S = steps[st];
@@ -164,14 +212,14 @@ __device__ __forceinline__ void peel_block4(const PeelParams& p, int64_t block, 
         if (S.f64) {
           v4d acc = {(double)y[i][0], (double)y[i][1], (double)y[i][2], (double)y[i][3]};
           for (int u = 0; u < S.nsub; ++u) {
-            const v4f v = xs[sub[u] * THREADS + tid];
+            const v4f v = xs.get(sub[u]);
             acc -= v4d{(double)v[0], (double)v[1], (double)v[2], (double)v[3]};
           }
           x = v4f{(float)acc[0], (float)acc[1], (float)acc[2], (float)acc[3]};
         } else {
           v4f sum = y[i], comp = {0.f, 0.f, 0.f, 0.f};
           for (int u = 0; u < S.nsub; ++u) {
-            const v4f v = -xs[sub[u] * THREADS + tid] - comp;
+            const v4f v = -xs.get(sub[u]) - comp;
             const v4f t = sum + v;
             comp = (t - sum) - v;
             sum = t;
@@ -179,7 +227,7 @@ __device__ __forceinline__ void peel_block4(const PeelParams& p, int64_t block, 
           x = sum;
         }
       }
-      if (S.slot >= 0) xs[S.slot * THREADS + tid] = x;
+      if (S.slot >= 0) xs.put(S.slot, x);
       if (S.write && active && r < valid) gstore4(p.C + (base + r) * p.ldc + c, x);
     }
   }
@@ -227,8 +275,9 @@ __global__ __launch_bounds__(128) void peel_grouped_kernel(const GroupDesc* __re
       stage_program(p, prog, 128);
       cur = prod;
     }
-    peel_block4<128>(p, b - pstart[prod], xs4, reinterpret_cast<const PeelStep*>(prog),
-                     prog + p.nsteps * (int)(sizeof(PeelStep) / 4));
+    LdsSlots<128> slots{xs4};
+    peel_block4<128, kBatch>(p, b - pstart[prod], slots, reinterpret_cast<const PeelStep*>(prog),
+                             prog + p.nsteps * (int)(sizeof(PeelStep) / 4));
   }
 }
 
@@ -264,14 +313,36 @@ __global__ __launch_bounds__(THREADS) void peel4s_kernel(PeelParams p) {
   extern __shared__ v4f xs4s[];
   int32_t* prog = reinterpret_cast<int32_t*>(xs4s + (size_t)p.nslots * THREADS);
   stage_program(p, prog, THREADS);
-  peel_block4<THREADS>(p, blockIdx.x, xs4s, reinterpret_cast<const PeelStep*>(prog),
-                       prog + p.nsteps * (int)(sizeof(PeelStep) / 4));
+  LdsSlots<THREADS> slots{xs4s};
+  peel_block4<THREADS, kBatch>(p, blockIdx.x, slots, reinterpret_cast<const PeelStep*>(prog),
+                               prog + p.nsteps * (int)(sizeof(PeelStep) / 4));
+}
+// The same with the slots in registers: 8 loads in flight per thread
+// instead of 16 and at most 128 registers per lane, so that four waves per
+// SIMD fit and a CU holds 8 workgroups (the 8192 x 4096 workload's 2048
+// workgroups in one round, where LDS slots allowed 6 per CU: peel 61 -> 50
+// us; 12 loads in flight gave 51 us).  The grouped peel keeps its LDS slots:
+// its persistent workgroups are not limited by how many a CU holds (the
+// batch's peel took the same 0.58 ms with register slots).
+constexpr int kBatchReg = 8;
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(4))) void peel4r_kernel(
+    PeelParams p) {
+  extern __shared__ int32_t prog_r[];
+  stage_program(p, prog_r, 128);
+  RegSlots slots;
+  peel_block4<128, kBatchReg>(p, blockIdx.x, slots, reinterpret_cast<const PeelStep*>(prog_r),
+                              prog_r + p.nsteps * (int)(sizeof(PeelStep) / 4));
 }
 hipError_t launch_peel(const PeelParams& p, hipStream_t stream) {
   if (p.nsteps == 0) return hipSuccess;
   if (p.grid == 1 && (p.N & 3) == 0 && (p.ldc & 3) == 0) {
-    const size_t lds = (size_t)p.nslots * 128 * 16 + peel_program_bytes(p.nsteps, p.nsubs);
     const int64_t blocks = (p.Mb * (p.N / 4) + 127) / 128;
+    const size_t prog = peel_program_bytes(p.nsteps, p.nsubs);
+    if (p.nslots <= kRegSlots && prog <= 64 * 1024 && blocks <= 0x7fffffff) {
+      hipLaunchKernelGGL(peel4r_kernel, dim3((unsigned)blocks), dim3(128), prog, stream, p);
+      return hipGetLastError();
+    }
+    const size_t lds = (size_t)p.nslots * 128 * 16 + prog;
     if (lds <= 160 * 1024 && blocks <= 0x7fffffff) {
       hipLaunchKernelGGL(peel4s_kernel<128>, dim3((unsigned)blocks), dim3(128), lds, stream, p);
       return hipGetLastError();
