@@ -144,6 +144,39 @@ def _every_erasure_pair_small_code_integer_exact():
     assert n_ok > 0 and n_bad >= 1     # (6,4,2) cannot be column-MDS
 
 
+def test_peel_register_and_lds_slots_integer_exact():
+    # The single-product peel keeps a program's live slots in registers when
+    # it needs at most 12 and in LDS otherwise.  The (12,8,4) code's
+    # straggler plans (seeds 0-5: 10-12 slots, release depth up to 14, FP64
+    # accumulation) and its FULL plan (13 slots), two-launch path, integer
+    # operands (every FP32 and FP64 operation exact), M ragged with an empty
+    # padding block: C must equal A.B.
+    bpx.set_fused_peel(0)
+    try:
+        code = lib_code(inputs.CODE_1284)
+        M, K, N = 32 * 20 + 5, 64, 260
+        A = inputs.integers(9, inputs.TAG_A, (M, K))
+        B = inputs.integers(9, inputs.TAG_B, (K, N))
+        R = A.astype(np.float64) @ B.astype(np.float64)
+        cases = []
+        for seed in range(6):
+            arrival, lost, _ = inputs.arrival_of(inputs.WORKLOADS["fp32_scale"], seed=seed)
+            cases.append((list(arrival), lost, bpx.MODE_STRAGGLER))
+        cases.append((list(range(12)), 0, bpx.MODE_FULL))
+        seen = set()
+        for order, lost, mode in cases:
+            plan = bpx.Plan(code, order, lost, mode, M, K, N)
+            assert plan.decodable
+            slots = plan.peel_program()["n_slots"]
+            seen.add(slots)
+            _say("peel slots", slots, "mode", mode, "depth", plan.info()["depth_max"])
+            C = run(plan, A, B)
+            assert np.array_equal(C.astype(np.float64), R), (slots, mode)
+        assert 12 in seen and 13 in seen     # both sides of the register limit
+    finally:
+        bpx.set_fused_peel(1)
+
+
 def test_small_workload_float_tolerance():
     w = inputs.WORKLOADS["fp32_small"]
     A, B = inputs.operands(w, seed=0)
